@@ -1,0 +1,161 @@
+/*
+ * pf_lbm.h -- C interface of the MI355X coupled multi-phase-field / lattice-Boltzmann step.
+ *
+ * Method: R. Schiedung, M. Tegeler, D. Medvedev, F. Varnik, "Simulation of Capillary-Driven
+ * Kinetics with Multi-Phase-Field and Lattice-Boltzmann Method" (arXiv:1902.10432), Sec. 3.
+ *
+ * One handle holds one periodic box (lattice spacing and time step 1) with nb rigid bodies, each
+ * represented by one solid phase field phi_a (a = 0..nb-1); the fluid phase fraction is
+ * 1 - sum_a phi_a (Sec. 3.1).  One call of the step advances, in this order:
+ *   pseudopotential force with solid wetting (Sec. 3.2.3), Guo-forced BGK collision (Sec. 3.2.1),
+ *   streaming with half-way bounce-back from moving walls, rest-population mass correction and
+ *   momentum exchange (Sec. 3.2.2), solid-solid repulsion (Sec. 3.1.2), rigid-body update
+ *   (Sec. 3.1.1), split MC-limited advection of each phase field with its body's rigid velocity
+ *   (Sec. 3.1.1, 3.3), multi-phase-field kinetics with the volume-restoring driving force
+ *   (Sec. 3.3), solid/fluid reclassification and node conversion (Sec. 3.2.2).
+ *
+ * Conventions
+ *   - Every function returns a status (PF_LBM_OK or a negative code) and never throws; the
+ *     message of the last failure is available from pf_lbm_last_error (per handle; with a NULL
+ *     handle, the message of the last failed pf_lbm_init in this process).
+ *   - Memory: the caller owns all device memory.  pf_lbm_init carves one caller-allocated
+ *     device workspace; the library calls no device allocator.  Host arrays passed in are read
+ *     during the call only.
+ *   - Streams: a handle is bound to the HIP stream given at init; pf_lbm_step and pf_lbm_fields
+ *     are asynchronous and stream-ordered; pf_lbm_forces synchronises the stream.  A handle is
+ *     not thread-safe.
+ *   - Fields are x-fastest arrays [nz][ny][nx] (phase fields [nb][nz][ny][nx]).
+ */
+#ifndef PF_LBM_H
+#define PF_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_LBM_MAX_BODIES 16
+
+typedef struct pf_lbm pf_lbm; /* opaque handle */
+
+enum {
+    PF_LBM_OK = 0,
+    PF_LBM_EINVAL = -1,       /* invalid argument or configuration                          */
+    PF_LBM_ENOMEM = -2,       /* workspace smaller than required, or a host allocation failed */
+    PF_LBM_EUNSUPPORTED = -3, /* valid for the method, not supported by this build          */
+    PF_LBM_EDEVICE = -4,      /* a HIP runtime call failed                                  */
+    PF_LBM_ENONFINITE = -5,   /* non-finite body force or state, or advection CFL above 1   */
+};
+
+enum { PF_LBM_D3Q19 = 19 };
+
+/* arithmetic / storage of the fluid populations and phase fields */
+enum { PF_LBM_FP64 = 0, PF_LBM_FP32 = 1 };
+
+/* step options (config.flags) */
+enum {
+    PF_LBM_KINETICS = 1,  /* multi-phase-field kinetics and volume term (Sec. 3.3)        */
+    PF_LBM_MOTION = 2,    /* integrate the rigid bodies (Sec. 3.1.1); off = all held still */
+    PF_LBM_REPULSION = 4, /* solid-solid repulsion (Sec. 3.1.2)                            */
+};
+
+/* pf_lbm_fields selectors */
+enum {
+    PF_LBM_FIELD_RHO = 0,   /* density sum_i f_i of the post-stream populations; 0 on solid nodes */
+    PF_LBM_FIELD_JX = 1,    /* momentum density sum_i c_i f_i (x, y, z); 0 on solid nodes         */
+    PF_LBM_FIELD_JY = 2,
+    PF_LBM_FIELD_JZ = 3,
+    PF_LBM_FIELD_SOLID = 4, /* 1 on solid nodes, 0 on fluid nodes                                 */
+    PF_LBM_FIELD_OWNER = 5, /* owning body of a solid node, -1 on fluid nodes                     */
+    PF_LBM_FIELD_PSI = 6,   /* pseudopotential of the last step (fluid: psi(rho); solid: psi(varrho)) */
+    PF_LBM_FIELD_PHI = 16,  /* PF_LBM_FIELD_PHI + a: phase field of body a                         */
+};
+
+/* destination element types of pf_lbm_fields */
+enum { PF_LBM_DST_F64 = 0, PF_LBM_DST_F32 = 1 };
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(pf_lbm_config): ABI check                                  */
+    int32_t nx, ny, nz;     /* periodic box, cells per axis (each >= 1)                          */
+    int32_t lattice;        /* PF_LBM_D3Q19                                                       */
+    int32_t precision;      /* PF_LBM_FP64 or PF_LBM_FP32                                         */
+    int32_t flags;          /* PF_LBM_KINETICS | PF_LBM_MOTION | PF_LBM_REPULSION                 */
+    double tau;             /* BGK relaxation time, > 1/2 (Sec. 3.2.1)                            */
+    double G;               /* pseudopotential coupling (Sec. 3.2.3)                              */
+    double rho0;            /* reference density of psi = 1 - exp(-rho/rho0), > 0 (Sec. 3.2.3)    */
+    double solid_threshold; /* a node is solid iff its fluid fraction is below this (Sec. 3.2.2)  */
+    double mobility;        /* M_ab, uniform over pairs (Sec. 3.3)                                */
+    double eta;             /* interface width of the kinetics, > 0 (Sec. 3.3)                    */
+    const double *sigma;    /* (nb+1) x (nb+1) row-major interface energies, index 0 = fluid      */
+                            /* phase; NULL = 1.0 solid/fluid, 0.5 solid/solid (Sec. 3.3)          */
+    double r_c, n_exp, e0;  /* repulsion range (0 < r_c <= 4), exponent, strength (Sec. 3.1.2)    */
+    double R_A;             /* redistribution radius of node conversion, 1 <= R_A <= sqrt(3)     */
+                            /* (Sec. 3.2.2)                                                        */
+    double fext[3];         /* uniform external force density on the fluid (0 in the paper)       */
+} pf_lbm_config;
+
+typedef struct {
+    double mass_density; /* rho_a: body mass = rho_a * sum(phi_a) at t = 0 (Sec. 3.3 table)    */
+    double wetting_rho;  /* varrho_a: a solid node acts as fluid of this density (Sec. 3.2.3) */
+    double v[3];         /* initial translational velocity                                      */
+    double w[3];         /* initial angular velocity                                            */
+    int32_t fixed;       /* nonzero: the body is never integrated (V, omega, X stay as given)   */
+} pf_lbm_body;
+
+/*
+ * Create a simulation.
+ *   cfg, n_bodies (0..PF_LBM_MAX_BODIES), bodies[n_bodies]: parameters and bodies.
+ *   rho0:  HOST FP64 [nz][ny][nx] initial density; the fluid starts at rest, f = f_eq(rho0, 0)
+ *          on fluid nodes (values on solid nodes are ignored).
+ *   phi0:  HOST FP64 [n_bodies][nz][ny][nx] initial phase fields in [0, 1] with sum <= 1 (may
+ *          be NULL when n_bodies == 0).  Body mass, centre (phi-weighted centroid, unwrapped
+ *          across the periodic boundary at the largest empty gap of the support), inertia
+ *          tensor and reference volume come from phi0.
+ *   workspace, ws_bytes: caller-owned device memory, 256-byte aligned.  With workspace == NULL
+ *          the call only writes the required size to *ws_bytes_needed and returns PF_LBM_OK.
+ *   hip_stream: hipStream_t the handle is bound to (NULL = default stream).
+ *   out: receives the handle (owned by the caller, released with pf_lbm_destroy).
+ * Errors: PF_LBM_EINVAL (bad sizes or parameters), PF_LBM_ENOMEM (ws_bytes too small),
+ *   PF_LBM_EUNSUPPORTED (lattice other than D3Q19, precision other than FP64/FP32),
+ *   PF_LBM_EDEVICE (HIP failure).  The call returns after the initial fields are on the device.
+ */
+int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *bodies, const double *rho0,
+                const double *phi0, void *workspace, size_t ws_bytes, void *hip_stream, pf_lbm **out,
+                size_t *ws_bytes_needed);
+
+/* Enqueue n_steps >= 0 time steps on the handle's stream (no host synchronisation).  Returns a
+ * pending error from the device (PF_LBM_ENONFINITE) only at the next pf_lbm_forces call. */
+int pf_lbm_step(pf_lbm *h, int32_t n_steps);
+
+/*
+ * Synchronise the stream and copy the body state to HOST arrays of n_bodies x 3 doubles each
+ * (any pointer may be NULL): F, T = total force and torque of the last step (momentum exchange
+ * + pseudopotential reaction + repulsion, torques about the centres); X = centre of mass;
+ * V = velocity; W = angular velocity (after the last step's update).  Returns
+ * PF_LBM_ENONFINITE if the device flagged a non-finite body state or an advection velocity
+ * above one cell per step since init.
+ */
+int pf_lbm_forces(pf_lbm *h, double *F, double *T, double *X, double *V, double *W);
+
+/* Write field `which` (PF_LBM_FIELD_*) of the current state into caller-owned DEVICE memory dst
+ * of nz*ny*nx elements of type dst_dtype (PF_LBM_DST_F64 or PF_LBM_DST_F32).  Asynchronous. */
+int pf_lbm_fields(pf_lbm *h, int32_t which, void *dst, int32_t dst_dtype);
+
+/* Diagnostics copied to a HOST array of 4 doubles (synchronises): steps taken, fluid-to-solid
+ * and solid-to-fluid conversions since init, conversions whose neighbourhood held no fluid node
+ * (their mass could not be handed on). */
+int pf_lbm_diagnostics(pf_lbm *h, double *out4);
+
+/* Release the handle (the workspace stays the caller's).  NULL is ignored. */
+void pf_lbm_destroy(pf_lbm *h);
+
+/* Message of the last failure on h (or of the last failed pf_lbm_init when h is NULL). */
+const char *pf_lbm_last_error(const pf_lbm *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_LBM_H */

@@ -1,0 +1,525 @@
+// C-ABI of the MI355X coupled multi-phase-field / lattice-Boltzmann step: workspace layout,
+// host-side body moments, the per-step launch sequence and read-out.  See include/pf_lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pf_lbm.h"
+#include "kernels_lbm.h"
+#include "kernels_pf.h"
+
+using namespace pfl;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t fA, fB, psi, phiA, phiB, mask, bodies, state, sigma, pforce, prep, pvol, total;
+};
+
+}  // namespace
+
+struct pf_lbm {
+    pf_lbm_config cfg;
+    int nb = 0;
+    int prec = PF_LBM_FP32;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    Layout L{};
+    long long N = 0, Np = 0;
+    int dense_blocks = 0, box_blocks = 1;
+    long long steps = 0;
+    std::vector<double> sigma;
+    std::string err;
+};
+
+namespace {
+
+int fail(pf_lbm *h, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                           \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail((h), PF_LBM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t real_size(int prec) { return prec == PF_LBM_FP64 ? 8 : 4; }
+
+Layout make_layout(long long Np, int nb, int prec, int box_blocks) {
+    const size_t rs = real_size(prec);
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.fA = take((size_t)19 * Np * rs);
+    L.fB = take((size_t)19 * Np * rs);
+    L.psi = take((size_t)Np * rs);
+    L.phiA = take((size_t)std::max(nb, 1) * Np * rs);
+    L.phiB = take((size_t)std::max(nb, 1) * Np * rs);
+    L.mask = take((size_t)Np);
+    L.bodies = take(sizeof(BodyDev) * std::max(nb, 1));
+    L.state = take(sizeof(StepState));
+    L.sigma = take(sizeof(double) * (nb + 1) * (nb + 1));
+    L.pforce = take(sizeof(double) * box_blocks * std::max(nb, 1) * 6);
+    L.prep = take(sizeof(double) * box_blocks * std::max(nb, 1) * 6);
+    L.pvol = take(sizeof(double) * box_blocks * std::max(nb, 1) * 2);
+    L.total = off;
+    return L;
+}
+
+double mimg_h(double d, double L) { return d - L * std::floor(d / L + 0.5); }
+
+// Support of a set of fields along one axis: occupied planes; the support is taken as the
+// contiguous run that starts right after the longest cyclic run of empty planes (first one on
+// ties).  Returns false when every plane is occupied.
+bool axis_gap(const std::vector<char> &occ, int &start, int &extent) {
+    const int L = (int)occ.size();
+    int best_len = 0, best_end = -1;
+    for (int k0 = 0; k0 < L; ++k0) {
+        if (occ[k0] || !occ[(k0 - 1 + L) % L]) continue;
+        int len = 0;
+        while (len < L && !occ[(k0 + len) % L]) ++len;
+        if (len > best_len) {
+            best_len = len;
+            best_end = (k0 + len - 1) % L;
+        }
+    }
+    if (best_len == 0) return false;
+    start = (best_end + 1) % L;
+    extent = L - best_len;
+    return true;
+}
+
+struct HostBody {
+    double M, Iinv[9], X[3], Vref;
+};
+
+// mass, centre (phi-weighted centroid in unwrapped coordinates; an axis without an empty plane
+// uses the circular mean), inertia tensor about the centre with minimum-image lever arms, and
+// the reference volume sum(phi), from the phase field at t = 0 (Sec. 3.1.1, 3.3)
+HostBody body_moments(const double *phi, int nx, int ny, int nz, double rho_s) {
+    const int n[3] = {nx, ny, nz};
+    HostBody hb{};
+    std::vector<char> occ[3] = {std::vector<char>(nx, 0), std::vector<char>(ny, 0), std::vector<char>(nz, 0)};
+    double sc[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+    const double PI = 3.14159265358979323846;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double p = phi[x + (long long)nx * (y + (long long)ny * z)];
+                if (p == 0.0) continue;
+                const int c[3] = {x, y, z};
+                for (int d = 0; d < 3; ++d) {
+                    occ[d][c[d]] = 1;
+                    sc[d] += p * std::cos(2.0 * PI * c[d] / n[d]);
+                    ss[d] += p * std::sin(2.0 * PI * c[d] / n[d]);
+                }
+            }
+    int start[3] = {0, 0, 0}, ext[3];
+    bool gap[3];
+    double c0[3];
+    for (int d = 0; d < 3; ++d) {
+        gap[d] = axis_gap(occ[d], start[d], ext[d]);
+        double a = std::atan2(ss[d], sc[d]);
+        if (a < 0) a += 2.0 * PI;
+        c0[d] = a * n[d] / (2.0 * PI);
+    }
+    auto unwrap = [&](int d, int k) {
+        return gap[d] ? (double)start[d] + (double)(((k - start[d]) % n[d] + n[d]) % n[d]) : c0[d] + mimg_h(k - c0[d], n[d]);
+    };
+    double vol = 0.0, m1[3] = {0, 0, 0};
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double p = phi[x + (long long)nx * (y + (long long)ny * z)];
+                if (p == 0.0) continue;
+                vol += p;
+                m1[0] += p * unwrap(0, x);
+                m1[1] += p * unwrap(1, y);
+                m1[2] += p * unwrap(2, z);
+            }
+    hb.Vref = vol;
+    hb.M = rho_s * vol;
+    for (int d = 0; d < 3; ++d) {
+        double X = vol > 0 ? m1[d] / vol : 0.0;
+        X -= n[d] * std::floor(X / n[d]);
+        hb.X[d] = X;
+    }
+    double I[9] = {0};
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double p = phi[x + (long long)nx * (y + (long long)ny * z)];
+                if (p == 0.0) continue;
+                const double r[3] = {mimg_h(x - hb.X[0], nx), mimg_h(y - hb.X[1], ny), mimg_h(z - hb.X[2], nz)};
+                const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) I[3 * i + j] += rho_s * p * ((i == j ? r2 : 0.0) - r[i] * r[j]);
+            }
+    // inverse by the adjugate; a degenerate tensor gets a zero inverse (no rotation)
+    double adj[9] = {I[4] * I[8] - I[5] * I[7], I[2] * I[7] - I[1] * I[8], I[1] * I[5] - I[2] * I[4],
+                     I[5] * I[6] - I[3] * I[8], I[0] * I[8] - I[2] * I[6], I[2] * I[3] - I[0] * I[5],
+                     I[3] * I[7] - I[4] * I[6], I[1] * I[6] - I[0] * I[7], I[0] * I[4] - I[1] * I[3]};
+    const double det = I[0] * adj[0] + I[1] * adj[3] + I[2] * adj[6];
+    const double scale = std::fabs(I[0]) + std::fabs(I[4]) + std::fabs(I[8]);
+    const bool ok = scale > 0.0 && std::fabs(det) > 1e-12 * scale * scale * scale;
+    for (int k = 0; k < 9; ++k) hb.Iinv[k] = ok ? adj[k] / det : 0.0;
+    return hb;
+}
+
+template <typename T>
+Prm<T> make_prm(const pf_lbm *h) {
+    Prm<T> p{};
+    p.nx = h->cfg.nx;
+    p.ny = h->cfg.ny;
+    p.nz = h->cfg.nz;
+    p.nb = h->nb;
+    p.N = (int)h->N;
+    p.Np = h->Np;
+    p.omega = (T)(1.0 / h->cfg.tau);
+    p.guo = (T)(1.0 - 0.5 / h->cfg.tau);
+    p.G = (T)h->cfg.G;
+    p.inv_rho0 = (T)(1.0 / h->cfg.rho0);
+    for (int d = 0; d < 3; ++d) p.fext[d] = (T)h->cfg.fext[d];
+    p.flags = h->cfg.flags;
+    p.threshold = h->cfg.solid_threshold;
+    p.mobility = h->cfg.mobility;
+    p.eta = h->cfg.eta;
+    p.r_c = h->cfg.r_c;
+    p.n_exp = h->cfg.n_exp;
+    p.e0 = h->cfg.e0;
+    p.R_A = h->cfg.R_A;
+    return p;
+}
+
+template <typename T>
+T *fbuf(pf_lbm *h, int which) {
+    return (T *)(h->ws + (which ? h->L.fB : h->L.fA));
+}
+
+template <typename T>
+void launch_kinetics(pf_lbm *h, const Prm<T> &p, int par, StepState *st, BodyDev *bodies, const double *sigma,
+                     const T *src, T *dst) {
+    dim3 g(h->box_blocks), b(256);
+    if (h->nb <= 1)
+        k_kinetics<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+    else if (h->nb <= 2)
+        k_kinetics<T, 2><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+    else if (h->nb <= 4)
+        k_kinetics<T, 4><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+    else if (h->nb <= 8)
+        k_kinetics<T, 8><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+    else
+        k_kinetics<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+}
+
+// one time step (Sec. 3): fluid, body forces + rigid update, phase fields, reclassification
+template <typename T>
+int enqueue_step(pf_lbm *h) {
+    const Prm<T> p = make_prm<T>(h);
+    const int par = (int)(h->steps & 1);
+    T *fc = fbuf<T>(h, par), *fn = fbuf<T>(h, par ^ 1);
+    T *psi = (T *)(h->ws + h->L.psi);
+    T *phiA = (T *)(h->ws + h->L.phiA), *phiB = (T *)(h->ws + h->L.phiB);
+    uint8_t *mask = (uint8_t *)(h->ws + h->L.mask);
+    BodyDev *bodies = (BodyDev *)(h->ws + h->L.bodies);
+    StepState *st = (StepState *)(h->ws + h->L.state);
+    const double *sigma = (const double *)(h->ws + h->L.sigma);
+    double *pforce = (double *)(h->ws + h->L.pforce), *prep = (double *)(h->ws + h->L.prep),
+           *pvol = (double *)(h->ws + h->L.pvol);
+    const dim3 gd(h->dense_blocks), gb(h->box_blocks), b(256);
+    hipStream_t s = h->stream;
+    const bool rep = h->nb > 1 && (h->cfg.flags & PF_LBM_REPULSION);
+
+    k_psi<T><<<gd, b, 0, s>>>(p, fc, mask, bodies, psi);
+    k_collide_stream<T><<<gd, b, 0, s>>>(p, fc, fn, psi, mask, bodies);
+    if (h->nb > 0) {
+        k_body_forces<T><<<gb, b, 0, s>>>(p, par, st, fc, fn, psi, mask, bodies, pforce, prep, rep ? h->box_blocks : 0);
+        k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, bodies, phiA, phiB, pvol);
+        k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, bodies, phiB, phiA, pvol);
+        k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, bodies, phiA, phiB, pvol);
+        launch_kinetics<T>(h, p, par, st, bodies, sigma, phiB, phiA);
+        k_classify<T><<<gb, b, 0, s>>>(p, par, st, phiA, phiB, mask, 0);
+        k_convert_gather<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
+        k_convert_finish<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
+        if (rep) k_repulsion<T><<<gb, b, 0, s>>>(p, par, st, mask, bodies, prep);
+    }
+    HIPCHK(h, hipGetLastError());
+    ++h->steps;
+    return PF_LBM_OK;
+}
+
+template <typename T>
+int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, const double *phi0,
+                const std::vector<BodyDev> &bodies, const StepState &st0) {
+    const Prm<T> p = make_prm<T>(h);
+    hipStream_t s = h->stream;
+    T *phiA = (T *)(h->ws + h->L.phiA), *phiB = (T *)(h->ws + h->L.phiB);
+    uint8_t *mask = (uint8_t *)(h->ws + h->L.mask);
+    double *tmp = (double *)(h->ws + h->L.fB);  // staging for FP64 host fields
+    StepState *st = (StepState *)(h->ws + h->L.state);
+    const dim3 b(256);
+    const int gd = std::max(1, std::min(h->dense_blocks, 65535));
+    (void)bodies_in;
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->L.bodies, bodies.data(), sizeof(BodyDev) * std::max(h->nb, 1),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(st, &st0, sizeof(StepState), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->L.sigma, h->sigma.data(), sizeof(double) * h->sigma.size(),
+                             hipMemcpyHostToDevice, s));
+    k_zero_mask<T><<<gd, b, 0, s>>>(p, mask);
+    // phase fields, one body at a time through the staging area
+    for (int a = 0; a < h->nb; ++a) {
+        HIPCHK(h, hipMemcpyAsync(tmp, phi0 + (size_t)a * h->N, sizeof(double) * h->N, hipMemcpyHostToDevice, s));
+        Prm<T> q = p;
+        q.nb = 1;
+        k_init_phi<T><<<gd, b, 0, s>>>(q, tmp, phiA + (size_t)a * h->Np, phiB + (size_t)a * h->Np);
+        HIPCHK(h, hipStreamSynchronize(s));
+    }
+    if (h->nb > 0) k_classify<T><<<dim3(h->box_blocks), b, 0, s>>>(p, 0, st, phiA, nullptr, mask, 1);
+    HIPCHK(h, hipMemcpyAsync(tmp, rho0, sizeof(double) * h->N, hipMemcpyHostToDevice, s));
+    T *fA = fbuf<T>(h, 0), *fB = fbuf<T>(h, 1);
+    // populations at rest into fA (reads the staged density in the fB area) ...
+    k_init_f<T><<<gd, b, 0, s>>>(p, tmp, mask, fA);
+    HIPCHK(h, hipStreamSynchronize(s));
+    // ... then clear fB (solid nodes keep empty populations in both buffers)
+    HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)19 * h->Np * sizeof(T), s));
+    HIPCHK(h, hipMemcpyAsync(st, &st0, sizeof(StepState), hipMemcpyHostToDevice, s));
+    // repulsion of the initial configuration feeds the first step's body update
+    if (h->nb > 1 && (h->cfg.flags & PF_LBM_REPULSION)) {
+        k_repulsion<T><<<dim3(h->box_blocks), b, 0, s>>>(p, 0, st, mask, (BodyDev *)(h->ws + h->L.bodies),
+                                                         (double *)(h->ws + h->L.prep));
+    }
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    return PF_LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *bodies, const double *rho0,
+                const double *phi0, void *workspace, size_t ws_bytes, void *hip_stream, pf_lbm **out,
+                size_t *ws_bytes_needed) {
+    g_init_error.clear();
+    if (!cfg) return fail(nullptr, PF_LBM_EINVAL, "cfg is NULL");
+    if (cfg->struct_size < sizeof(pf_lbm_config))
+        return fail(nullptr, PF_LBM_EINVAL, "cfg->struct_size %u < %zu", cfg->struct_size, sizeof(pf_lbm_config));
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return fail(nullptr, PF_LBM_EINVAL, "grid sizes must be >= 1");
+    const long long N = (long long)cfg->nx * cfg->ny * cfg->nz;
+    if (N * 19 >= (1LL << 31) * 8LL || N >= (1LL << 31)) return fail(nullptr, PF_LBM_EINVAL, "grid too large");
+    if (n_bodies < 0 || n_bodies > PF_LBM_MAX_BODIES)
+        return fail(nullptr, PF_LBM_EINVAL, "n_bodies must be in [0, %d]", PF_LBM_MAX_BODIES);
+    if (cfg->lattice != PF_LBM_D3Q19) return fail(nullptr, PF_LBM_EUNSUPPORTED, "only the D3Q19 lattice is built");
+    if (cfg->precision != PF_LBM_FP64 && cfg->precision != PF_LBM_FP32)
+        return fail(nullptr, PF_LBM_EUNSUPPORTED, "precision must be PF_LBM_FP64 or PF_LBM_FP32");
+    if (!(cfg->tau > 0.5)) return fail(nullptr, PF_LBM_EINVAL, "tau must exceed 1/2");
+    if (!(cfg->rho0 > 0.0)) return fail(nullptr, PF_LBM_EINVAL, "rho0 must be positive");
+    if (!(cfg->eta > 0.0)) return fail(nullptr, PF_LBM_EINVAL, "eta must be positive");
+    if (!(cfg->R_A >= 1.0 - 1e-12 && cfg->R_A <= std::sqrt(3.0) + 1e-12))
+        return fail(nullptr, PF_LBM_EUNSUPPORTED, "R_A must lie in [1, sqrt(3)]");
+    if ((cfg->flags & PF_LBM_REPULSION) && !(cfg->r_c > 0.0 && cfg->r_c <= 4.0))
+        return fail(nullptr, PF_LBM_EUNSUPPORTED, "r_c must lie in (0, 4]");
+    if (!(cfg->solid_threshold > 0.0 && cfg->solid_threshold < 1.0))
+        return fail(nullptr, PF_LBM_EINVAL, "solid_threshold must lie in (0, 1)");
+    if (n_bodies > 0 && (!bodies || !phi0)) return fail(nullptr, PF_LBM_EINVAL, "bodies and phi0 are required");
+    for (int a = 0; a < n_bodies; ++a)
+        if (!(bodies[a].mass_density > 0.0)) return fail(nullptr, PF_LBM_EINVAL, "body %d: mass_density must be > 0", a);
+
+    const long long Np = (N + 63) / 64 * 64;
+    // box kernels: one block per ~2048 cells of the initial box, at most 1024 blocks
+    std::vector<char> occ[3] = {std::vector<char>(cfg->nx, 0), std::vector<char>(cfg->ny, 0),
+                                std::vector<char>(cfg->nz, 0)};
+    bool any = false;
+    if (n_bodies > 0) {
+        for (int a = 0; a < n_bodies; ++a)
+            for (long long i = 0; i < N; ++i)
+                if (phi0[(size_t)a * N + i] > 0.0) {
+                    const int x = (int)(i % cfg->nx), y = (int)((i / cfg->nx) % cfg->ny), z = (int)(i / ((long long)cfg->nx * cfg->ny));
+                    occ[0][x] = occ[1][y] = occ[2][z] = 1;
+                    any = true;
+                }
+    }
+    int box[6] = {0, 0, 0, -1, -1, -1};
+    if (any) {
+        const int n[3] = {cfg->nx, cfg->ny, cfg->nz};
+        for (int d = 0; d < 3; ++d) {
+            int start = 0, ext = n[d];
+            if (!axis_gap(occ[d], start, ext)) {
+                start = 0;
+                ext = n[d];
+            }
+            int lo = start - 3, hi = start + ext - 1 + 3;
+            if (hi - lo + 1 >= n[d]) {
+                lo = 0;
+                hi = n[d] - 1;
+            }
+            box[d] = lo;
+            box[3 + d] = hi;
+        }
+    }
+    const long long vol0 = any ? (long long)(box[3] - box[0] + 1) * (box[4] - box[1] + 1) * (box[5] - box[2] + 1) : 0;
+    const int box_blocks = (int)std::max(1LL, std::min(1024LL, (vol0 + 2047) / 2048));
+    const Layout L = make_layout(Np, n_bodies, cfg->precision, box_blocks);
+    if (ws_bytes_needed) *ws_bytes_needed = L.total;
+    if (!workspace) return PF_LBM_OK;
+    if (!out) return fail(nullptr, PF_LBM_EINVAL, "out is NULL");
+    if (ws_bytes < L.total) return fail(nullptr, PF_LBM_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    if ((uintptr_t)workspace % ALIGN) return fail(nullptr, PF_LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (!rho0) return fail(nullptr, PF_LBM_EINVAL, "rho0 is NULL");
+
+    pf_lbm *h = new (std::nothrow) pf_lbm();
+    if (!h) return fail(nullptr, PF_LBM_ENOMEM, "host allocation failed");
+    h->cfg = *cfg;
+    h->cfg.sigma = nullptr;
+    h->nb = n_bodies;
+    h->prec = cfg->precision;
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char *)workspace;
+    h->L = L;
+    h->N = N;
+    h->Np = Np;
+    h->dense_blocks = (int)((N + 255) / 256);
+    h->box_blocks = box_blocks;
+    const int np1 = n_bodies + 1;
+    h->sigma.assign((size_t)np1 * np1, 0.0);
+    for (int a = 0; a < np1; ++a)
+        for (int b = 0; b < np1; ++b)
+            h->sigma[a * np1 + b] = cfg->sigma ? cfg->sigma[a * np1 + b] : (a == b ? 0.0 : ((a == 0 || b == 0) ? 1.0 : 0.5));
+
+    std::vector<BodyDev> bd(std::max(n_bodies, 1));
+    std::memset(bd.data(), 0, sizeof(BodyDev) * bd.size());
+    for (int a = 0; a < n_bodies; ++a) {
+        const HostBody hb = body_moments(phi0 + (size_t)a * N, cfg->nx, cfg->ny, cfg->nz, bodies[a].mass_density);
+        BodyDev &B = bd[a];
+        B.M = hb.M;
+        for (int k = 0; k < 9; ++k) B.Iinv[k] = hb.Iinv[k];
+        for (int d = 0; d < 3; ++d) {
+            B.X[d] = hb.X[d];
+            B.V[d] = bodies[a].v[d];
+            B.W[d] = bodies[a].w[d];
+        }
+        B.psi_s = 1.0 - std::exp(-bodies[a].wetting_rho / cfg->rho0);
+        B.Vref = hb.Vref;
+        B.fixed = bodies[a].fixed ? 1 : 0;
+    }
+    StepState st0;
+    std::memset(&st0, 0, sizeof st0);
+    for (int d = 0; d < 6; ++d) st0.box[0][d] = st0.box[1][d] = box[d];
+    for (int d = 0; d < 3; ++d) {
+        st0.tight[d] = INT32_MAX;
+        st0.tight[3 + d] = INT32_MIN;
+    }
+    int rc = h->prec == PF_LBM_FP64 ? init_device<double>(h, bodies, rho0, phi0, bd, st0)
+                                    : init_device<float>(h, bodies, rho0, phi0, bd, st0);
+    if (rc != PF_LBM_OK) {
+        g_init_error = h->err;
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return PF_LBM_OK;
+}
+
+int pf_lbm_step(pf_lbm *h, int32_t n_steps) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    if (n_steps < 0) return fail(h, PF_LBM_EINVAL, "n_steps must be >= 0");
+    for (int k = 0; k < n_steps; ++k) {
+        const int rc = h->prec == PF_LBM_FP64 ? enqueue_step<double>(h) : enqueue_step<float>(h);
+        if (rc != PF_LBM_OK) return rc;
+    }
+    return PF_LBM_OK;
+}
+
+int pf_lbm_forces(pf_lbm *h, double *F, double *T, double *X, double *V, double *W) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    std::vector<BodyDev> bd(std::max(h->nb, 1));
+    StepState st;
+    HIPCHK(h, hipMemcpyAsync(bd.data(), h->ws + h->L.bodies, sizeof(BodyDev) * bd.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&st, h->ws + h->L.state, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int a = 0; a < h->nb; ++a)
+        for (int d = 0; d < 3; ++d) {
+            if (F) F[3 * a + d] = bd[a].F[d];
+            if (T) T[3 * a + d] = bd[a].T[d];
+            if (X) X[3 * a + d] = bd[a].X[d];
+            if (V) V[3 * a + d] = bd[a].V[d];
+            if (W) W[3 * a + d] = bd[a].W[d];
+        }
+    if (st.err & 1u) return fail(h, PF_LBM_ENONFINITE, "non-finite body force or state");
+    if (st.err & 2u) return fail(h, PF_LBM_ENONFINITE, "advection velocity above one cell per step");
+    return PF_LBM_OK;
+}
+
+int pf_lbm_fields(pf_lbm *h, int32_t which, void *dst, int32_t dst_dtype) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    if (!dst) return fail(h, PF_LBM_EINVAL, "dst is NULL");
+    const bool ok = (which >= 0 && which <= 6) || (which >= PF_LBM_FIELD_PHI && which < PF_LBM_FIELD_PHI + h->nb);
+    if (!ok) return fail(h, PF_LBM_EINVAL, "unknown field %d", which);
+    if (dst_dtype != PF_LBM_DST_F64 && dst_dtype != PF_LBM_DST_F32) return fail(h, PF_LBM_EINVAL, "bad dst dtype");
+    const int par = (int)(h->steps & 1);
+    const dim3 g(std::max(1, std::min(h->dense_blocks, 65535))), b(256);
+    const uint8_t *mask = (const uint8_t *)(h->ws + h->L.mask);
+    if (h->prec == PF_LBM_FP64) {
+        const Prm<double> p = make_prm<double>(h);
+        const double *f = fbuf<double>(h, par), *psi = (const double *)(h->ws + h->L.psi),
+                     *phi = (const double *)(h->ws + h->L.phiA);
+        if (dst_dtype == PF_LBM_DST_F64)
+            k_fields<double, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
+        else
+            k_fields<double, float><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
+    } else {
+        const Prm<float> p = make_prm<float>(h);
+        const float *f = fbuf<float>(h, par), *psi = (const float *)(h->ws + h->L.psi),
+                    *phi = (const float *)(h->ws + h->L.phiA);
+        if (dst_dtype == PF_LBM_DST_F64)
+            k_fields<float, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
+        else
+            k_fields<float, float><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
+    }
+    HIPCHK(h, hipGetLastError());
+    return PF_LBM_OK;
+}
+
+int pf_lbm_diagnostics(pf_lbm *h, double *out4) {
+    if (!h || !out4) return fail(h, PF_LBM_EINVAL, "handle or output is NULL");
+    StepState st;
+    HIPCHK(h, hipMemcpyAsync(&st, h->ws + h->L.state, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    out4[0] = (double)h->steps;
+    out4[1] = (double)st.n_f2s;
+    out4[2] = (double)st.n_s2f;
+    out4[3] = (double)st.n_lost;
+    return PF_LBM_OK;
+}
+
+void pf_lbm_destroy(pf_lbm *h) { delete h; }
+
+const char *pf_lbm_last_error(const pf_lbm *h) { return h ? h->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"
