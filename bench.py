@@ -1,0 +1,169 @@
+#!/usr/bin/env python
+"""Throughput of the coupled phase-field / lattice-Boltzmann step on one MI355X.
+
+Default workload: two spheres (R = 20, nominal surface gap 4) joined by a liquid bridge of 2 % of
+one sphere's volume, 30 degree wetting, 128^3 D3Q19, FP32 populations and phase fields, rigid-body
+motion and phase-field kinetics on.  A step is the whole coupled step (every kernel).  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line: MLUPS (all nodes x steps / s), the step's algorithmic fraction of HBM peak,
+the dominant kernel's roofline (algorithmic bytes per launch over its mean launch time measured
+with HIP events on the library's stream), and the FP64 CPU oracle timed on the host on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PF+LBM step MLUPS & % HBM peak; fp16-store/batched vs fp32 at force err≤1e-3"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+KERNEL = "k_collide_stream"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1902_10432_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def step_bytes_per_cell(real: int) -> float:
+    """Algorithmic bytes of one coupled step per node: 19 populations read and written, the
+    pseudopotential written once and read once, the mask read once (phase-field work on the
+    interface band is below 1 %)."""
+    return 2 * 19 * real + 2 * real + 1
+
+
+def kernel_bytes(n_fluid: int, n_solid: int, real: int) -> float:
+    """Algorithmic bytes of one collide-stream launch: a fluid node reads and writes its 19
+    populations and reads its own pseudopotential and mask byte (neighbour values are re-reads
+    of the same arrays); a solid node reads its mask byte only."""
+    return n_fluid * (2 * 19 * real + real + 1) + n_solid * 1.0
+
+
+def traffic_from_profile(workload: str, precision: str, sha: str):
+    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{workload}_{precision}_hbm.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    if prof.get("source_sha") != sha:
+        return None  # the kernel changed since the counters were taken
+    return prof.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, seconds: float) -> dict:
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.Oracle.max_threads()
+    o = oracle.Oracle(w.params, w.bodies, w.rho0, w.phi0)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(seconds / max(t1, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": round(w.cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the same {w.shape[2]}x{w.shape[1]}x{w.shape[0]} workload in FP64 "
+                      f"after 1 warm-up step ({dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="two_spheres_bridge")
+    ap.add_argument("--n", type=int, default=None, help="grid size override (cubic)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1902_10432_amd.simulation import Simulation
+    from pflbm_inputs import make_workload
+
+    kw = {"n": args.n} if args.n else {}
+    w = make_workload(args.workload, **kw)
+    real = 4 if args.precision == "fp32" else 8
+    log(f"workload {w.name} {w.shape} bodies={len(w.bodies)} {args.precision}")
+    sim = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=args.precision)
+    stream = sim.stream
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    ms_per_step = ms / args.steps
+    mlups = w.cells * args.steps / (ms / 1e3) / 1e6
+    pct_step = mlups * 1e6 * step_bytes_per_cell(real) / (HBM_PEAK_GBS * 1e9)
+    log(f"timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), {mlups:.1f} MLUPS")
+
+    # dominant kernel: mean launch time from events recorded around it on the library's stream
+    sim.timing(True)
+    sim.step(args.steps)
+    tm = sim.timing(False)
+    solid = sim.field("solid").sum().item()
+    n_solid = int(solid)
+    n_fluid = w.cells - n_solid
+    kb = kernel_bytes(n_fluid, n_solid, real)
+    achieved = kb / (tm["kernel_ms"] / 1e3) / 1e9
+    sha = source_sha()
+    traffic = traffic_from_profile(w.name, args.precision, sha)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL,
+                "kernel_ms": round(tm["kernel_ms"], 5), "bytes_per_launch": kb}
+    b = sim.bodies()
+    ok = all(math.isfinite(v) for v in np.asarray(b["F"]).ravel())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real == 4 else "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name} {w.shape[2]}x{w.shape[1]}x{w.shape[0]} D3Q19, {len(w.bodies)} bodies, "
+                               f"motion+kinetics on", "cells": w.cells, "precision": args.precision},
+        "pct_hbm_step_algorithmic": round(pct_step, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "finite_forces": ok,
+        "source_sha": sha,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -148,6 +148,13 @@ int pf_lbm_fields(pf_lbm *h, int32_t which, void *dst, int32_t dst_dtype);
  * (their mass could not be handed on). */
 int pf_lbm_diagnostics(pf_lbm *h, double *out4);
 
+/* Measurement: pf_lbm_timing(h, 1, NULL) starts recording HIP events on the handle's stream
+ * around the fused collide-stream kernel and around each whole step of the following
+ * pf_lbm_step calls (at most 4096 steps); pf_lbm_timing(h, 0, out4) synchronises, stops and
+ * writes to a HOST array of 4 doubles: timed steps, mean collide-stream kernel time (ms), mean
+ * step time (ms), and 0 (reserved). */
+int pf_lbm_timing(pf_lbm *h, int32_t enable, double *out4);
+
 /* Release the handle (the workspace stays the caller's).  NULL is ignored. */
 void pf_lbm_destroy(pf_lbm *h);
 

@@ -39,7 +39,7 @@ PF_LBM_DST_F64 = 0
 PF_LBM_DST_F32 = 1
 
 EXPORTED = ("pf_lbm_init", "pf_lbm_step", "pf_lbm_forces", "pf_lbm_fields", "pf_lbm_diagnostics",
-            "pf_lbm_destroy", "pf_lbm_last_error")
+            "pf_lbm_timing", "pf_lbm_destroy", "pf_lbm_last_error")
 
 
 class PfLbmConfig(C.Structure):
@@ -93,6 +93,8 @@ def load_library():
     lib.pf_lbm_fields.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]
     lib.pf_lbm_diagnostics.restype = C.c_int
     lib.pf_lbm_diagnostics.argtypes = [C.c_void_p, dp]
+    lib.pf_lbm_timing.restype = C.c_int
+    lib.pf_lbm_timing.argtypes = [C.c_void_p, C.c_int32, dp]
     lib.pf_lbm_destroy.restype = None
     lib.pf_lbm_destroy.argtypes = [C.c_void_p]
     lib.pf_lbm_last_error.restype = C.c_char_p
@@ -138,6 +140,13 @@ def pf_lbm_fields(h, which: int, dst_ptr: int, dst_dtype: int) -> int:
 def pf_lbm_diagnostics(h):
     out = np.zeros(4)
     rc = load_library().pf_lbm_diagnostics(h, _dptr(out))
+    return rc, out
+
+
+def pf_lbm_timing(h, enable: int):
+    """enable=1 starts event timing; enable=0 stops it and returns (status, out[4])."""
+    out = np.zeros(4)
+    rc = load_library().pf_lbm_timing(h, int(enable), _dptr(out) if not enable else None)
     return rc, out
 
 

@@ -8,6 +8,8 @@
 
 #include <utility>
 
+#include "../../include/pf_lbm.h"
+
 namespace pfl {
 
 // ---- D3Q19 (Sec. 3.2.1 prints D3Q27; both share c_s^2 = 1/3 and the second and fourth
@@ -37,9 +39,23 @@ __device__ __forceinline__ void sfor(F &&f) {
     sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// ---- mask byte: bit 7 solid, bit 6 became solid this step, bit 5 became fluid this step,
-// bits 0-4 owning body of a solid node
-constexpr uint8_t M_SOLID = 0x80, M_F2S = 0x40, M_S2F = 0x20, M_OWNER = 0x1f;
+// ---- cell word (one uint32 per node): bit 31 solid, bit 30 became solid this step, bit 29
+// became fluid this step, bits 24-28 owning body of a solid node, bit i (1..18) set when the
+// neighbour in direction i is solid (kept current inside the body box by k_neighbour_bits)
+using cell_t = uint32_t;
+constexpr uint32_t C_SOLID = 1u << 31, C_F2S = 1u << 30, C_S2F = 1u << 29, C_NBMASK = 0x7FFFEu;
+__device__ __forceinline__ int owner_of(uint32_t w) { return (int)((w >> 24) & 31u); }
+__device__ __forceinline__ uint32_t solid_word(int owner) { return C_SOLID | ((uint32_t)owner << 24); }
+
+// load / store at a byte offset from a uniform base (lets the compiler use scalar-base addressing)
+template <typename T>
+__device__ __forceinline__ T ldb(const T *base, uint32_t byteoff) {
+    return *(const T *)((const char *)base + byteoff);
+}
+template <typename T>
+__device__ __forceinline__ void stb(T *base, uint32_t byteoff, T v) {
+    *(T *)((char *)base + byteoff) = v;
+}
 
 // ---- body table (FP64, device resident)
 struct BodyDev {
@@ -55,15 +71,45 @@ struct BodyDev {
 // Per-step state shared by the kernels.  Boxes are in unwrapped lattice coordinates
 // [lo, hi] per axis (hi - lo + 1 <= n); box[p] is read by step parity p, written for the next.
 struct StepState {
-    int32_t box[2][6];           // lo x, lo y, lo z, hi x, hi y, hi z
-    int32_t tight[6];            // atomic min / max accumulators of the phase-field support
-    uint32_t done[4];            // last-block counters: 0 forces, 1 volume sums, 2 box
-    uint32_t err;                // bit 0 non-finite body state, bit 1 advection CFL above 1
-    uint32_t pad;
+    int32_t box[2][6];            // lo x, lo y, lo z, hi x, hi y, hi z
+    uint32_t err;                 // bit 0 non-finite body state, bit 1 advection CFL above 1
+    uint32_t events;              // nonzero when this step's reclassification changed any node
     unsigned long long n_f2s, n_s2f, n_lost;
+    float srad[PF_LBM_MAX_BODIES];  // largest distance of a solid node from its body's centre
 };
 
+// per-block results of the reclassification kernel, combined at the start of the next step
+struct ClassifyPart {
+    int32_t lo[3], hi[3];           // bounding box of the phase-field support (unwrapped)
+    uint32_t f2s, s2f;              // nodes that became solid / fluid
+    float srad[PF_LBM_MAX_BODIES];  // per-body largest solid-node distance from the centre
+    double vol[PF_LBM_MAX_BODIES];  // per-body sum of phi
+    uint32_t icnt[PF_LBM_MAX_BODIES];  // per-body count of interface nodes floor < phi < 1
+};
+
+// Deterministic sum of v[0..n) by one wave: lane l accumulates v[l + 64 m] into four
+// interleaved partial sums (independent loads in flight), combined in a fixed order, then a fixed
+// xor-shuffle tree across the lanes.
+__device__ __forceinline__ double wave_sum_array(const double *v, int n) {
+    const int lane = (int)(threadIdx.x & 63);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int j = lane;
+    for (; j + 192 < n; j += 256) {
+        s0 += v[j];
+        s1 += v[j + 64];
+        s2 += v[j + 128];
+        s3 += v[j + 192];
+    }
+    for (; j < n; j += 64) s0 += v[j];
+    double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
 __device__ __forceinline__ double mimg(double d, double L) { return d - L * floor(d / L + 0.5); }
+// the same with a precomputed 1/L (hot loops)
+__device__ __forceinline__ double mimg_r(double d, double L, double invL) { return d - L * floor(d * invL + 0.5); }
 
 __device__ __forceinline__ int wrapi(int i, int n) {
     int r = i % n;
@@ -112,19 +158,127 @@ struct Prm {
     T fext[3];
     int flags;       // PF_LBM_* step flags
     double threshold, mobility, eta, r_c, n_exp, e0, R_A;
+    double inv_n[3]; // 1 / nx, 1 / ny, 1 / nz
 };
 
-// box cell k (0 <= k < box volume) -> unwrapped coordinates
-__device__ __forceinline__ void box_cell(const int32_t *b, long long k, int &ux, int &uy, int &uz) {
-    const int ex = b[3] - b[0] + 1, ey = b[4] - b[1] + 1;
-    ux = b[0] + (int)(k % ex);
-    long long t = k / ex;
-    uy = b[1] + (int)(t % ey);
-    uz = b[2] + (int)(t / ey);
+// floor(k / d) for 0 <= k < 2^31, 0 < d, through a double reciprocal and one correction
+__device__ __forceinline__ int fast_div(int k, int d, double inv_d) {
+    int q = (int)((double)k * inv_d);
+    const int r = k - q * d;
+    q += (r >= d) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
 }
-__device__ __forceinline__ long long box_volume(const int32_t *b) {
-    if (b[3] < b[0] || b[4] < b[1] || b[5] < b[2]) return 0;
-    return (long long)(b[3] - b[0] + 1) * (b[4] - b[1] + 1) * (b[5] - b[2] + 1);
+
+// iteration over the cells of a box [lo, hi] (unwrapped coordinates, hi - lo + 1 <= n per axis)
+struct BoxIter {
+    int lo[3], ex, ey, vol, n[3];
+    double inv_ex, inv_ey;
+    __device__ __forceinline__ BoxIter(const int32_t *b, int nx, int ny, int nz) {
+        lo[0] = b[0];
+        lo[1] = b[1];
+        lo[2] = b[2];
+        ex = b[3] - b[0] + 1;
+        ey = b[4] - b[1] + 1;
+        const int ez = b[5] - b[2] + 1;
+        vol = (ex > 0 && ey > 0 && ez > 0) ? ex * ey * ez : 0;
+        inv_ex = ex > 0 ? 1.0 / ex : 0.0;
+        inv_ey = ey > 0 ? 1.0 / ey : 0.0;
+        n[0] = nx;
+        n[1] = ny;
+        n[2] = nz;
+    }
+    // cell k -> unwrapped (u) and wrapped (c) coordinates; the box spans at most one period
+    __device__ __forceinline__ void cell(int k, int *u, int *c) const {
+        const int t = fast_div(k, ex, inv_ex);
+        const int zz = fast_div(t, ey, inv_ey);
+        u[0] = lo[0] + (k - t * ex);
+        u[1] = lo[1] + (t - zz * ey);
+        u[2] = lo[2] + zz;
+        for (int d = 0; d < 3; ++d) {
+            int v = u[d];
+            v += v < 0 ? n[d] : 0;
+            v -= v >= n[d] ? n[d] : 0;
+            c[d] = v;
+        }
+    }
+};
+
+// periodic wrap of i when it lies within one period of [0, n)
+__device__ __forceinline__ int wrap1(int i, int n) {
+    i += i < 0 ? n : 0;
+    return i - (i >= n ? n : 0);
+}
+
+// periodic wrap of i when it lies within two periods of [0, n) (offsets of up to 2 cells on axes
+// as short as one cell)
+__device__ __forceinline__ int wrap2(int i, int n) {
+    i += i < 0 ? n : 0;
+    i += i < 0 ? n : 0;
+    i -= i >= n ? n : 0;
+    i -= i >= n ? n : 0;
+    return i;
+}
+
+// Run by one whole wave at the start of a step: combine the per-block reclassification results
+// of the previous step in a fixed order and publish
+//  * this step's box: phase-field support + 3-cell margin, the whole axis once it would wrap onto
+//    itself, lower corner brought into [0, n) (so unwrapped coordinates stay below 2 n);
+//  * the per-body solid radii (bound the repulsion search);
+//  * the volume driving term of each body, h_a = (4 eta / pi^2) (V_ref - sum phi_a) /
+//    #{floor < phi_a < 1} (Sec. 3.3; 0 without interface nodes), into the body table;
+// and clear the event flag for this step's reclassification.
+__device__ __forceinline__ void publish_step_state(int parity, int nx, int ny, int nz, int nb, double eta,
+                                                   StepState *st, BodyDev *bodies, const ClassifyPart *cpart,
+                                                   int nblk) {
+    const int lane = (int)(threadIdx.x & 63);
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int j = lane; j < nblk; j += 64)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = min(lo[d], cpart[j].lo[d]);
+            hi[d] = max(hi[d], cpart[j].hi[d]);
+        }
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = wave_min(lo[d]);
+        hi[d] = wave_max(hi[d]);
+    }
+    if (lane == 0) {
+        const int n[3] = {nx, ny, nz};
+        const bool empty = lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2];
+        for (int d = 0; d < 3; ++d) {
+            int l = lo[d] - 3, h = hi[d] + 3;
+            if (h - l + 1 >= n[d]) {
+                l = 0;
+                h = n[d] - 1;
+            } else {
+                const int s = wrap2(l, n[d]) - l;
+                l += s;
+                h += s;
+            }
+            st->box[parity][d] = empty ? 0 : l;
+            st->box[parity][3 + d] = empty ? -1 : h;
+        }
+        st->events = 0u;
+    }
+    const double PI = 3.14159265358979323846;
+    for (int b = 0; b < nb; ++b) {
+        float r = 0.0f;
+        double v = 0.0;
+        int c = 0;
+        for (int j = lane; j < nblk; j += 64) {
+            r = fmaxf(r, cpart[j].srad[b]);
+            v += cpart[j].vol[b];
+            c += (int)cpart[j].icnt[b];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
+        v = wave_sum(v);
+        c = wave_sum(c);
+        if (lane == 0) {
+            st->srad[b] = r;
+            bodies[b].h = c > 0 ? (4.0 * eta / (PI * PI)) * (bodies[b].Vref - v) / (double)c : 0.0;
+        }
+    }
 }
 
 }  // namespace pfl

@@ -7,23 +7,58 @@
 namespace pfl {
 
 // Pseudopotential psi = 1 - exp(-rho/rho0) of every fluid node; a solid node carries the value
-// of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.
+// of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.  With bodies, the
+// first wave of the first block also publishes the step's box, solid radii, volume terms and
+// event flag from the previous reclassification (publish_step_state): that short reduction hides
+// behind the dense pass instead of costing a launch of its own.
 template <typename T>
-__global__ __launch_bounds__(256) void k_psi(Prm<T> p, const T *__restrict__ f, const uint8_t *__restrict__ mask,
-                                             const BodyDev *__restrict__ bodies, T *__restrict__ psi) {
+__global__ __launch_bounds__(256) void k_psi(Prm<T> p, int parity, const T *__restrict__ f,
+                                             const cell_t *__restrict__ mask, BodyDev *bodies, T *__restrict__ psi,
+                                             StepState *st, const ClassifyPart *__restrict__ cpart, int cblk) {
     const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    if (idx >= p.N) return;
-    const uint8_t m = mask[idx];
-    T out;
-    if (m & M_SOLID) {
-        out = (T)bodies[m & M_OWNER].psi_s;
-    } else {
-        T r = T(0);
-        sfor<19>([&](auto I) { r += f[(long long)I * p.Np + idx]; });
-        out = -expm1(-r * p.inv_rho0);
+    if (idx < p.N) {  // flat 1-D launch: no neighbours needed
+        const cell_t m = mask[idx];
+        T out;
+        if (m & C_SOLID) {
+            out = (T)bodies[owner_of(m)].psi_s;
+        } else {
+            T r = T(0);
+            sfor<19>([&](auto I) { r += f[(long long)I * p.Np + idx]; });
+            out = -expm1(-r * p.inv_rho0);
+        }
+        psi[idx] = out;
     }
-    psi[idx] = out;
+    if (cpart && blockIdx.x == 0 && threadIdx.x < 64)
+        publish_step_state(parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart, cblk);
 }
+
+// periodic neighbour offsets of one cell as unsigned index deltas (the sum with the cell index
+// wraps modulo 2^32 onto the neighbour's index, which lets loads use a scalar base + 32-bit
+// offset)
+struct NbrU {
+    uint32_t xp, xm, yp, ym, zp, zm;
+    // scale: bytes per element for byte offsets, 1 for element indices
+    __device__ __forceinline__ NbrU(int x, int y, int z, int nx, int ny, int nz, int scale) {
+        const int pl = nx * ny;
+        xp = (uint32_t)((x == nx - 1 ? 1 - nx : 1) * scale);
+        xm = (uint32_t)((x == 0 ? nx - 1 : -1) * scale);
+        yp = (uint32_t)((y == ny - 1 ? (1 - ny) * nx : nx) * scale);
+        ym = (uint32_t)((y == 0 ? (ny - 1) * nx : -nx) * scale);
+        zp = (uint32_t)((z == nz - 1 ? (1 - nz) * pl : pl) * scale);
+        zm = (uint32_t)((z == 0 ? (nz - 1) * pl : -pl) * scale);
+    }
+    template <int I>
+    __device__ __forceinline__ uint32_t at(uint32_t idx) const {
+        uint32_t o = idx;
+        if constexpr (Dir<I>::x == 1) o += xp;
+        if constexpr (Dir<I>::x == -1) o += xm;
+        if constexpr (Dir<I>::y == 1) o += yp;
+        if constexpr (Dir<I>::y == -1) o += ym;
+        if constexpr (Dir<I>::z == 1) o += zp;
+        if constexpr (Dir<I>::z == -1) o += zm;
+        return o;
+    }
+};
 
 // periodic neighbour offsets of one cell (index deltas for +1 / -1 along each axis)
 struct Nbr {
@@ -45,12 +80,31 @@ struct Nbr {
 };
 
 // Rigid-body velocity V + omega x (p - X) at point p (minimum image), Sec. 3.1.1.
-__device__ __forceinline__ void wall_velocity(const BodyDev &B, double px, double py, double pz, double nx, double ny,
-                                              double nz, double &ux, double &uy, double &uz) {
-    const double rx = mimg(px - B.X[0], nx), ry = mimg(py - B.X[1], ny), rz = mimg(pz - B.X[2], nz);
+template <typename T>
+__device__ __forceinline__ void wall_velocity(const Prm<T> &p, const BodyDev &B, double px, double py, double pz,
+                                              double &ux, double &uy, double &uz) {
+    const double rx = mimg_r(px - B.X[0], p.nx, p.inv_n[0]), ry = mimg_r(py - B.X[1], p.ny, p.inv_n[1]),
+                 rz = mimg_r(pz - B.X[2], p.nz, p.inv_n[2]);
     ux = B.V[0] + (B.W[1] * rz - B.W[2] * ry);
     uy = B.V[1] + (B.W[2] * rx - B.W[0] * rz);
     uz = B.V[2] + (B.W[0] * ry - B.W[1] * rx);
+}
+
+// reciprocal: correctly rounded in FP64 (parity with the FP64 oracle), hardware rcp in FP32
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// 3-D launch (64 x 4 threads per block, grid ceil(nx/64) x ceil(ny/4) x nz) with the flat block
+// id remapped so that each XCD works on a contiguous range of planes.
+__device__ __forceinline__ bool cell_of_block(int nx, int ny, int &x, int &y, int &z) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int r = xcd_block(lin, gx * gy * gridDim.z);
+    const int bz = r / (gx * gy), rem = r - bz * gx * gy, by = rem / gx, bxx = rem - by * gx;
+    x = bxx * 64 + (int)threadIdx.x;
+    y = by * 4 + (int)threadIdx.y;
+    z = bz;
+    return x < nx && y < ny;
 }
 
 // One fluid node per thread: load its 19 post-stream populations, form the Shan-Chen/Benzi force
@@ -59,146 +113,193 @@ __device__ __forceinline__ void wall_velocity(const BodyDev &B, double px, doubl
 // population to its neighbour, or reflect it half-way into the node's own opposite slot with the
 // moving-wall term when the neighbour is solid.  The wall terms are taken back from the rest
 // population (Sec. 3.2.1, 3.2.2, 3.2.3).  Solid nodes are skipped and receive nothing.
+//
+// Arithmetic is organised by opposite pairs (c_opp = -c): with cu = c.v, cF = c.F,
+//   f*_i = (1 - 1/tau) f_i + w (even + odd),  f*_opp = (1 - 1/tau) f_opp + w (even - odd),
+//   even = rho/tau (1 - 3/2 v.v) - 3 g v.F + 9/2 rho/tau cu^2 + 9 g cu cF,  odd = 3 rho/tau cu + 3 g cF,
+// g = 1 - 1/(2 tau), which is the BGK relaxation to the second-order equilibrium plus the Guo term.
 template <typename T>
 __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__restrict__ fin, T *__restrict__ fout,
-                                                        const T *__restrict__ psi, const uint8_t *__restrict__ mask,
+                                                        const T *__restrict__ psi, const cell_t *__restrict__ mask,
                                                         const BodyDev *__restrict__ bodies) {
-    const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    if (idx >= p.N) return;
-    if (mask[idx] & M_SOLID) return;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int x = idx % nx, yz = idx / nx, y = yz % ny, z = yz / ny;
-    const Nbr nb(x, y, z, nx, ny, nz);
+    int x, y, z;
+    if (!cell_of_block(nx, ny, x, y, z)) return;
+    const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
+    const cell_t w0 = mask[idx];
+    if (w0 & C_SOLID) return;
+    const uint32_t solid_dirs = w0 & C_NBMASK;
+    const uint32_t ib = idx * (uint32_t)sizeof(T);
+    const NbrU nb(x, y, z, nx, ny, nz, (int)sizeof(T));
     const long long Np = p.Np;
 
     T f[19];
-    sfor<19>([&](auto I) { f[I] = fin[(long long)I * Np + idx]; });
-    T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
-    sfor<19>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        rho += f[i];
-        if constexpr (Dir<i>::x == 1) jx += f[i];
-        if constexpr (Dir<i>::x == -1) jx -= f[i];
-        if constexpr (Dir<i>::y == 1) jy += f[i];
-        if constexpr (Dir<i>::y == -1) jy -= f[i];
-        if constexpr (Dir<i>::z == 1) jz += f[i];
-        if constexpr (Dir<i>::z == -1) jz -= f[i];
+    sfor<19>([&](auto I) { f[I] = ldb(fin + (long long)I * Np, ib); });
+    // moments from pair sums and differences
+    T rho = f[0], jx = T(0), jy = T(0), jz = T(0);
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * decltype(K)::value + 1;  // i and i + 1 are opposite
+        const T sp = f[i] + f[i + 1], dm = f[i] - f[i + 1];
+        rho += sp;
+        if constexpr (Dir<i>::x == 1) jx += dm;
+        if constexpr (Dir<i>::x == -1) jx -= dm;
+        if constexpr (Dir<i>::y == 1) jy += dm;
+        if constexpr (Dir<i>::y == -1) jy -= dm;
+        if constexpr (Dir<i>::z == 1) jz += dm;
+        if constexpr (Dir<i>::z == -1) jz -= dm;
     });
 
-    // pseudopotential force and solid-neighbour map
-    T sx = T(0), sy = T(0), sz = T(0);
-    uint32_t solid_dirs = 0;
-    uint8_t nbm[19];
-    sfor<19>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (i > 0) {
-            const int n = idx + nb.template off<i>();
-            const T wp = Dir<i>::template w<T>() * psi[n];
-            if constexpr (Dir<i>::x != 0) sx += T(Dir<i>::x) * wp;
-            if constexpr (Dir<i>::y != 0) sy += T(Dir<i>::y) * wp;
-            if constexpr (Dir<i>::z != 0) sz += T(Dir<i>::z) * wp;
-            nbm[i] = mask[n];
-            if (nbm[i] & M_SOLID) solid_dirs |= 1u << i;
+    // pseudopotential force from pair differences of the neighbours' psi
+    T s1x = T(0), s1y = T(0), s1z = T(0), s2x = T(0), s2y = T(0), s2z = T(0);
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * decltype(K)::value + 1;
+        const T dp = ldb(psi, nb.template at<i>(ib)) - ldb(psi, nb.template at<i + 1>(ib));
+        if constexpr (Dir<i>::c2 == 1) {
+            if constexpr (Dir<i>::x != 0) s1x += T(Dir<i>::x) * dp;
+            if constexpr (Dir<i>::y != 0) s1y += T(Dir<i>::y) * dp;
+            if constexpr (Dir<i>::z != 0) s1z += T(Dir<i>::z) * dp;
+        } else {
+            if constexpr (Dir<i>::x != 0) s2x += T(Dir<i>::x) * dp;
+            if constexpr (Dir<i>::y != 0) s2y += T(Dir<i>::y) * dp;
+            if constexpr (Dir<i>::z != 0) s2z += T(Dir<i>::z) * dp;
         }
     });
-    const T gp = -p.G * psi[idx];
-    const T Fx = gp * sx + p.fext[0], Fy = gp * sy + p.fext[1], Fz = gp * sz + p.fext[2];
+    const T gp = -p.G * ldb(psi, ib);
+    const T w1 = T(1.0 / 18.0), w2 = T(1.0 / 36.0);
+    const T Fx = gp * (w1 * s1x + w2 * s2x) + p.fext[0];
+    const T Fy = gp * (w1 * s1y + w2 * s2y) + p.fext[1];
+    const T Fz = gp * (w1 * s1z + w2 * s2z) + p.fext[2];
 
     // half-force velocity; an empty node has v = 0
     T ux = T(0), uy = T(0), uz = T(0);
     if (rho > T(0)) {
-        const T inv = T(1) / rho;
+        const T inv = recip(rho);
         ux = (jx + T(0.5) * Fx) * inv;
         uy = (jy + T(0.5) * Fy) * inv;
         uz = (jz + T(0.5) * Fz) * inv;
     }
-    const T uu = ux * ux + uy * uy + uz * uz;
-    const T uF = ux * Fx + uy * Fy + uz * Fz;
-    const T om = p.omega, guo = p.guo;
-
-    // collision: f* = f - (f - f_eq)/tau + (1 - 1/(2 tau)) w [3 (c - v).F + 9 (c.v)(c.F)]
-    sfor<19>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+    const T om = p.omega, g = p.guo, omr = om * rho;
+    const T A = omr * (T(1) - T(1.5) * (ux * ux + uy * uy + uz * uz)) - T(3) * g * (ux * Fx + uy * Fy + uz * Fz);
+    const T B = T(3) * omr, C = T(4.5) * omr, D = T(3) * g, E = T(9) * g, keep = T(1) - om;
+    f[0] = keep * f[0] + Dir<0>::template w<T>() * A;
+    sfor<9>([&](auto K) {
+        constexpr int i = 2 * decltype(K)::value + 1;
         constexpr T w = Dir<i>::template w<T>();
         const T cu = T(Dir<i>::x) * ux + T(Dir<i>::y) * uy + T(Dir<i>::z) * uz;
         const T cF = T(Dir<i>::x) * Fx + T(Dir<i>::y) * Fy + T(Dir<i>::z) * Fz;
-        const T feq = w * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
-        const T Fi = guo * w * (T(3) * (cF - uF) + T(9) * cu * cF);
-        f[i] = f[i] - om * (f[i] - feq) + Fi;
+        const T even = A + cu * (C * cu + E * cF);
+        const T odd = B * cu + D * cF;
+        f[i] = keep * f[i] + w * (even + odd);
+        f[i + 1] = keep * f[i + 1] + w * (even - odd);
     });
 
     // streaming
+    if (!solid_dirs) {
+        sfor<19>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0) stb(fout + (long long)i * Np, nb.template at<i>(ib), f[i]);
+        });
+        stb(fout, ib, f[0]);
+        return;
+    }
+    const NbrU ne(x, y, z, nx, ny, nz, 1);
     T drho = T(0);
     sfor<19>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (i > 0) {
             if (!(solid_dirs & (1u << i))) {
-                fout[(long long)i * Np + idx + nb.template off<i>()] = f[i];
+                stb(fout + (long long)i * Np, nb.template at<i>(ib), f[i]);
             } else {
                 // reflected into direction opp(i) with g = -2 rho w_i (c_i . u_w) / c_s^2, u_w at
                 // the link midpoint x + c_i / 2
-                const BodyDev &B = bodies[nbm[i] & M_OWNER];
+                const BodyDev &Bd = bodies[owner_of(mask[ne.template at<i>(idx)])];
                 double uwx, uwy, uwz;
-                wall_velocity(B, x + 0.5 * Dir<i>::x, y + 0.5 * Dir<i>::y, z + 0.5 * Dir<i>::z, nx, ny, nz, uwx, uwy, uwz);
+                wall_velocity(p, Bd, x + 0.5 * Dir<i>::x, y + 0.5 * Dir<i>::y, z + 0.5 * Dir<i>::z, uwx, uwy, uwz);
                 const double cuw = Dir<i>::x * uwx + Dir<i>::y * uwy + Dir<i>::z * uwz;
-                const T g = T(-6.0 * Dir<i>::template w<double>() * cuw) * rho;
-                fout[(long long)Dir<i>::opp * Np + idx] = f[i] + g;
-                drho += g;
+                const T gw = T(-6.0 * Dir<i>::template w<double>() * cuw) * rho;
+                stb(fout + (long long)Dir<i>::opp * Np, ib, f[i] + gw);
+                drho += gw;
             }
         }
     });
-    fout[idx] = f[0] - drho;
+    stb(fout, ib, f[0] - drho);
 }
 
-// Per-body sums over the fluid nodes next to solid nodes (box-restricted):
-//   momentum exchange  c_i (2 f*_i + g) for each link from a fluid node into body b, recovered
-//   from the reflected population f_opp(i) = f*_i + g written by k_collide_stream;
-//   pseudopotential reaction  +G psi(x) w_i psi(varrho_b) c_i (opposite of the fluid's share);
-//   torques about X_b with the link midpoint as lever arm.
-// Each wave reduces its contributions per touched body (64-lane shuffles) into LDS in a fixed
-// order; blocks write FP64 partials; the last block to finish sums all partials (and the
-// repulsion partials of the previous classification) in block order, stores F, T and advances
-// the bodies: V += F/M, X += V, omega += I^-1 T (Sec. 3.1.1).  Deterministic, no float atomics.
+// Per-body force and torque sums of the step, one box node per thread (Sec. 3.1.1, 3.1.2, 3.2.2):
+//  * fluid nodes next to solid nodes: momentum exchange c_i (2 f*_i + g) for each link into body
+//    b, recovered from the reflected population f_opp(i) = f*_i + g written by k_collide_stream,
+//    plus the pseudopotential reaction +G psi(x) w_i psi(varrho_b) c_i (opposite of the fluid's
+//    share), with the link midpoint as lever arm;
+//  * solid nodes (repulsion enabled): between a node p of body b1 and a node q of body b2 > b1
+//    with |p - q| < r_c, f = e0 (n/r_c) (p - q)/|p - q| |(|p - q| - r_c)/r_c|^(n-1) on b1 at p
+//    and -f on b2 at q; only nodes within r_c of a higher-index body's solid radius search.
+// Torques are about the body centres X_b (minimum image).  Each wave reduces its contributions
+// per touched body (64-lane shuffles) into LDS in a fixed order and every block writes FP64
+// partials [body * 6 + component][block], summed by the first advection sweep (k_advect), which
+// also advances the bodies.
 template <typename T>
-__global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, StepState *st, const T *__restrict__ fin,
-                                                     const T *__restrict__ fpost, const T *__restrict__ psi,
-                                                     const uint8_t *__restrict__ mask, BodyDev *bodies,
-                                                     double *part, const double *rep_part, int rep_blocks) {
+__global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, const StepState *st,
+                                                     const T *__restrict__ fin, const T *__restrict__ fpost,
+                                                     const T *__restrict__ psi, const cell_t *__restrict__ mask,
+                                                     const BodyDev *__restrict__ bodies, double *part) {
     __shared__ double acc[4][PF_LBM_MAX_BODIES][6];
-    __shared__ uint32_t ticket;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nbod = p.nb;
     for (int k = tid; k < 4 * PF_LBM_MAX_BODIES * 6; k += 256) (&acc[0][0][0])[k] = 0.0;
     __syncthreads();
-    const int32_t *bx = st->box[parity];
-    const long long vol = box_volume(bx);
+    const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
-    const long long stride = (long long)gridDim.x * 256;
-    for (long long base = (long long)blockIdx.x * 256; base < vol; base += stride) {
-        const long long k = base + tid;
+    const bool rep = nbod > 1 && (p.flags & PF_LBM_REPULSION);
+    const double rc = p.r_c, ne = p.n_exp, e0 = p.e0;
+    const int R = rep ? (int)ceil(rc) : 0;
+    for (int base = blockIdx.x * 256; base < it.vol; base += gridDim.x * 256) {
+        const int k = base + tid;
         uint32_t touched = 0;
-        int x = 0, y = 0, z = 0, idx = 0;
+        int x = 0, y = 0, z = 0, idx = 0, b1 = -1;
+        bool fluid = false;
         T rho = T(0), ps0 = T(0);
-        if (k < vol) {
-            int ux, uy, uz;
-            box_cell(bx, k, ux, uy, uz);
-            x = wrapi(ux, nx);
-            y = wrapi(uy, ny);
-            z = wrapi(uz, nz);
+        if (k < it.vol) {
+            int u[3], c[3];
+            it.cell(k, u, c);
+            x = c[0];
+            y = c[1];
+            z = c[2];
             idx = x + nx * (y + ny * z);
-            if (!(mask[idx] & M_SOLID)) {
-                const Nbr nb(x, y, z, nx, ny, nz);
-                sfor<19>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    if constexpr (i > 0) {
-                        const uint8_t mn = mask[idx + nb.template off<i>()];
-                        if (mn & M_SOLID) touched |= 1u << (mn & M_OWNER);
+            const cell_t w0 = mask[idx];
+            if (!(w0 & C_SOLID)) {
+                fluid = true;
+                if (w0 & C_NBMASK) {
+                    const Nbr nb(x, y, z, nx, ny, nz);
+                    sfor<19>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        if constexpr (i > 0) {
+                            if (w0 & (1u << i)) touched |= 1u << owner_of(mask[idx + nb.template off<i>()]);
+                        }
+                    });
+                    if (touched) {
+                        sfor<19>([&](auto I) { rho += fin[(long long)I * Np + idx]; });
+                        ps0 = psi[idx];
                     }
-                });
-                if (touched) {
-                    sfor<19>([&](auto I) { rho += fin[(long long)I * Np + idx]; });
-                    ps0 = psi[idx];
+                }
+            } else if (rep) {
+                b1 = owner_of(w0);
+                bool near = false;
+                for (int b2 = b1 + 1; b2 < nbod; ++b2) {
+                    const BodyDev &B = bodies[b2];
+                    const double rx = mimg_r(x - B.X[0], nx, p.inv_n[0]), ry = mimg_r(y - B.X[1], ny, p.inv_n[1]),
+                                 rz = mimg_r(z - B.X[2], nz, p.inv_n[2]);
+                    if (sqrt(rx * rx + ry * ry + rz * rz) < (double)st->srad[b2] + rc + 1e-3) near = true;
+                }
+                if (near) {
+                    for (int dz = -R; dz <= R; ++dz)
+                        for (int dy = -R; dy <= R; ++dy)
+                            for (int dx = -R; dx <= R; ++dx) {
+                                const int d2 = dx * dx + dy * dy + dz * dz;
+                                if (d2 == 0 || !((double)d2 < rc * rc)) continue;
+                                const cell_t mq = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
+                                if ((mq & C_SOLID) && owner_of(mq) > b1) touched |= (1u << b1) | (1u << owner_of(mq));
+                            }
                 }
             }
         }
@@ -207,18 +308,18 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, StepS
             const int b = __ffs(wt) - 1;
             wt &= wt - 1;
             double v[6] = {0, 0, 0, 0, 0, 0};
-            if (touched & (1u << b)) {
+            if ((touched & (1u << b)) && fluid) {
                 const Nbr nb(x, y, z, nx, ny, nz);
                 const BodyDev &B = bodies[b];
                 sfor<19>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     if constexpr (i > 0) {
                         const int n = idx + nb.template off<i>();
-                        const uint8_t mn = mask[n];
-                        if ((mn & M_SOLID) && (mn & M_OWNER) == b) {
+                        const cell_t mn = mask[n];
+                        if ((mn & C_SOLID) && owner_of(mn) == b) {
                             const double px = x + 0.5 * Dir<i>::x, py = y + 0.5 * Dir<i>::y, pz = z + 0.5 * Dir<i>::z;
                             double uwx, uwy, uwz;
-                            wall_velocity(B, px, py, pz, nx, ny, nz, uwx, uwy, uwz);
+                            wall_velocity(p, B, px, py, pz, uwx, uwy, uwz);
                             const double cuw = Dir<i>::x * uwx + Dir<i>::y * uwy + Dir<i>::z * uwz;
                             const T g = T(-6.0 * Dir<i>::template w<double>() * cuw) * rho;
                             const T fr = fpost[(long long)Dir<i>::opp * Np + idx];
@@ -226,7 +327,8 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, StepS
                             const double s = (double)(T(2) * fr - g) +
                                              (double)(p.G * ps0 * Dir<i>::template w<T>() * psi[n]);
                             const double fx = s * Dir<i>::x, fy = s * Dir<i>::y, fz = s * Dir<i>::z;
-                            const double rx = mimg(px - B.X[0], nx), ry = mimg(py - B.X[1], ny), rz = mimg(pz - B.X[2], nz);
+                            const double rx = mimg_r(px - B.X[0], nx, p.inv_n[0]), ry = mimg_r(py - B.X[1], ny, p.inv_n[1]),
+                                         rz = mimg_r(pz - B.X[2], nz, p.inv_n[2]);
                             v[0] += fx;
                             v[1] += fy;
                             v[2] += fz;
@@ -236,6 +338,38 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, StepS
                         }
                     }
                 });
+            } else if (touched & (1u << b)) {
+                for (int dz = -R; dz <= R; ++dz)
+                    for (int dy = -R; dy <= R; ++dy)
+                        for (int dx = -R; dx <= R; ++dx) {
+                            const int d2 = dx * dx + dy * dy + dz * dz;
+                            if (d2 == 0 || !((double)d2 < rc * rc)) continue;
+                            const cell_t mq = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
+                            if (!(mq & C_SOLID)) continue;
+                            const int b2 = owner_of(mq);
+                            if (b2 <= b1 || (b != b1 && b != b2)) continue;
+                            const double r = sqrt((double)d2);
+                            const double mag = e0 * (ne / rc) * pow(fabs((r - rc) / rc), ne - 1.0);
+                            // force on b1 at p, directed from q to p
+                            double fx = -dx / r * mag, fy = -dy / r * mag, fz = -dz / r * mag;
+                            double ax = x, ay = y, az = z;
+                            if (b == b2) {
+                                fx = -fx;
+                                fy = -fy;
+                                fz = -fz;
+                                ax = x + dx;
+                                ay = y + dy;
+                                az = z + dz;
+                            }
+                            const BodyDev &B = bodies[b];
+                            const double rx = mimg(ax - B.X[0], nx), ry = mimg(ay - B.X[1], ny), rz = mimg(az - B.X[2], nz);
+                            v[0] += fx;
+                            v[1] += fy;
+                            v[2] += fz;
+                            v[3] += ry * fz - rz * fy;
+                            v[4] += rz * fx - rx * fz;
+                            v[5] += rx * fy - ry * fx;
+                        }
             }
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
@@ -247,42 +381,8 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, StepS
     __syncthreads();
     for (int k = tid; k < nbod * 6; k += 256) {
         const int b = k / 6, c = k % 6;
-        part[((long long)blockIdx.x * nbod + b) * 6 + c] = ((acc[0][b][c] + acc[1][b][c]) + acc[2][b][c]) + acc[3][b][c];
+        part[(long long)k * gridDim.x + blockIdx.x] = ((acc[0][b][c] + acc[1][b][c]) + acc[2][b][c]) + acc[3][b][c];
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) ticket = atomicAdd(&st->done[0], 1u);
-    __syncthreads();
-    if (ticket != gridDim.x - 1) return;
-    // ---- last block: fixed-order totals and the rigid-body update
-    __threadfence();
-    __shared__ double tot[PF_LBM_MAX_BODIES * 6];
-    for (int k = tid; k < nbod * 6; k += 256) {
-        double s = 0.0;
-        for (int j = 0; j < (int)gridDim.x; ++j) s += part[(long long)j * nbod * 6 + k];
-        for (int j = 0; j < rep_blocks; ++j) s += rep_part[(long long)j * nbod * 6 + k];
-        tot[k] = s;
-    }
-    __syncthreads();
-    if (tid < nbod) {
-        BodyDev &B = bodies[tid];
-        const double *F = &tot[tid * 6], *Tq = &tot[tid * 6 + 3];
-        bool finite = true;
-        for (int d = 0; d < 3; ++d) {
-            B.F[d] = F[d];
-            B.T[d] = Tq[d];
-            finite = finite && isfinite(F[d]) && isfinite(Tq[d]);
-        }
-        if ((p.flags & 2) && !B.fixed) {
-            for (int d = 0; d < 3; ++d) B.V[d] += F[d] / B.M;
-            for (int d = 0; d < 3; ++d) B.X[d] += B.V[d];
-            for (int d = 0; d < 3; ++d)
-                B.W[d] += B.Iinv[3 * d + 0] * Tq[0] + B.Iinv[3 * d + 1] * Tq[1] + B.Iinv[3 * d + 2] * Tq[2];
-        }
-        for (int d = 0; d < 3; ++d) finite = finite && isfinite(B.V[d]) && isfinite(B.X[d]) && isfinite(B.W[d]);
-        if (!finite) atomicOr(&st->err, 1u);
-    }
-    if (tid == 0) st->done[0] = 0;
 }
 
 }  // namespace pfl

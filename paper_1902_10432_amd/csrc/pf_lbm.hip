@@ -25,7 +25,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t fA, fB, psi, phiA, phiB, mask, bodies, state, sigma, pforce, prep, pvol, total;
+    size_t fA, fB, psi, phiA, phiB, mask, bodies, state, sigma, pforce, cpart, total;
 };
 
 }  // namespace
@@ -39,9 +39,17 @@ struct pf_lbm {
     Layout L{};
     long long N = 0, Np = 0;
     int dense_blocks = 0, box_blocks = 1;
+    int box_grid = 1, force_grid = 1;  // grids of the box kernels and of the force scan
     long long steps = 0;
     std::vector<double> sigma;
     std::string err;
+    // measurement events (pf_lbm_timing)
+    bool timing = false;
+    int timed = 0;
+    std::vector<hipEvent_t> ev;  // 4 per timed step: step start, kernel start, kernel end, step end
+    // two steps (even, odd parity) captured once and replayed
+    hipGraphExec_t graph = nullptr;
+    bool graph_failed = false;
 };
 
 namespace {
@@ -67,7 +75,7 @@ int fail(pf_lbm *h, int code, const char *fmt, ...) {
 
 size_t real_size(int prec) { return prec == PF_LBM_FP64 ? 8 : 4; }
 
-Layout make_layout(long long Np, int nb, int prec, int box_blocks) {
+Layout make_layout(long long Np, int nb, int prec, int box_grid, int force_grid) {
     const size_t rs = real_size(prec);
     Layout L{};
     size_t off = 0;
@@ -79,15 +87,16 @@ Layout make_layout(long long Np, int nb, int prec, int box_blocks) {
     L.fA = take((size_t)19 * Np * rs);
     L.fB = take((size_t)19 * Np * rs);
     L.psi = take((size_t)Np * rs);
-    L.phiA = take((size_t)std::max(nb, 1) * Np * rs);
-    L.phiB = take((size_t)std::max(nb, 1) * Np * rs);
-    L.mask = take((size_t)Np);
-    L.bodies = take(sizeof(BodyDev) * std::max(nb, 1));
+    // phase fields are FP64 in every form: the advection increments of slow, heavy bodies lie
+    // far below the FP32 resolution of phi
+    L.phiA = take((size_t)std::max(nb, 1) * Np * sizeof(double));
+    L.phiB = take((size_t)std::max(nb, 1) * Np * sizeof(double));
+    L.mask = take((size_t)Np * sizeof(cell_t));
+    L.bodies = take(2 * sizeof(BodyDev) * std::max(nb, 1));  // current / next, by step parity
     L.state = take(sizeof(StepState));
     L.sigma = take(sizeof(double) * (nb + 1) * (nb + 1));
-    L.pforce = take(sizeof(double) * box_blocks * std::max(nb, 1) * 6);
-    L.prep = take(sizeof(double) * box_blocks * std::max(nb, 1) * 6);
-    L.pvol = take(sizeof(double) * box_blocks * std::max(nb, 1) * 2);
+    L.pforce = take(sizeof(double) * force_grid * std::max(nb, 1) * 6);
+    L.cpart = take(sizeof(ClassifyPart) * box_grid);
     L.total = off;
     return L;
 }
@@ -214,6 +223,9 @@ Prm<T> make_prm(const pf_lbm *h) {
     p.n_exp = h->cfg.n_exp;
     p.e0 = h->cfg.e0;
     p.R_A = h->cfg.R_A;
+    p.inv_n[0] = 1.0 / h->cfg.nx;
+    p.inv_n[1] = 1.0 / h->cfg.ny;
+    p.inv_n[2] = 1.0 / h->cfg.nz;
     return p;
 }
 
@@ -223,9 +235,9 @@ T *fbuf(pf_lbm *h, int which) {
 }
 
 template <typename T>
-void launch_kinetics(pf_lbm *h, const Prm<T> &p, int par, StepState *st, BodyDev *bodies, const double *sigma,
-                     const T *src, T *dst) {
-    dim3 g(h->box_blocks), b(256);
+void launch_kinetics(pf_lbm *h, const Prm<T> &p, int par, const StepState *st, const BodyDev *bodies,
+                     const double *sigma, const double *src, double *dst) {
+    dim3 g(h->box_grid), b(256);
     if (h->nb <= 1)
         k_kinetics<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
     else if (h->nb <= 2)
@@ -245,30 +257,48 @@ int enqueue_step(pf_lbm *h) {
     const int par = (int)(h->steps & 1);
     T *fc = fbuf<T>(h, par), *fn = fbuf<T>(h, par ^ 1);
     T *psi = (T *)(h->ws + h->L.psi);
-    T *phiA = (T *)(h->ws + h->L.phiA), *phiB = (T *)(h->ws + h->L.phiB);
-    uint8_t *mask = (uint8_t *)(h->ws + h->L.mask);
-    BodyDev *bodies = (BodyDev *)(h->ws + h->L.bodies);
+    double *phiA = (double *)(h->ws + h->L.phiA), *phiB = (double *)(h->ws + h->L.phiB);
+    cell_t *mask = (cell_t *)(h->ws + h->L.mask);
+    BodyDev *btab = (BodyDev *)(h->ws + h->L.bodies);
+    const int nbm = std::max(h->nb, 1);
+    BodyDev *cur = btab + par * nbm, *next = btab + (par ^ 1) * nbm;
     StepState *st = (StepState *)(h->ws + h->L.state);
     const double *sigma = (const double *)(h->ws + h->L.sigma);
-    double *pforce = (double *)(h->ws + h->L.pforce), *prep = (double *)(h->ws + h->L.prep),
-           *pvol = (double *)(h->ws + h->L.pvol);
-    const dim3 gd(h->dense_blocks), gb(h->box_blocks), b(256);
+    double *pforce = (double *)(h->ws + h->L.pforce);
+    ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
+    const dim3 gd(h->dense_blocks), b(256);
     hipStream_t s = h->stream;
-    const bool rep = h->nb > 1 && (h->cfg.flags & PF_LBM_REPULSION);
-
-    k_psi<T><<<gd, b, 0, s>>>(p, fc, mask, bodies, psi);
-    k_collide_stream<T><<<gd, b, 0, s>>>(p, fc, fn, psi, mask, bodies);
-    if (h->nb > 0) {
-        k_body_forces<T><<<gb, b, 0, s>>>(p, par, st, fc, fn, psi, mask, bodies, pforce, prep, rep ? h->box_blocks : 0);
-        k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, bodies, phiA, phiB, pvol);
-        k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, bodies, phiB, phiA, pvol);
-        k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, bodies, phiA, phiB, pvol);
-        launch_kinetics<T>(h, p, par, st, bodies, sigma, phiB, phiA);
-        k_classify<T><<<gb, b, 0, s>>>(p, par, st, phiA, phiB, mask, 0);
-        k_convert_gather<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
-        k_convert_finish<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
-        if (rep) k_repulsion<T><<<gb, b, 0, s>>>(p, par, st, mask, bodies, prep);
+    hipEvent_t *ev = nullptr;
+    if (h->timing && h->timed < 4096) {
+        if ((int)h->ev.size() < 4 * (h->timed + 1)) {
+            for (int k = 0; k < 4; ++k) {
+                hipEvent_t e;
+                HIPCHK(h, hipEventCreate(&e));
+                h->ev.push_back(e);
+            }
+        }
+        ev = &h->ev[4 * h->timed];
+        ++h->timed;
     }
+    if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
+    k_psi<T><<<gd, b, 0, s>>>(p, par, fc, mask, cur, psi, st, h->nb > 0 ? cpart : nullptr, h->box_grid);
+    if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
+    k_collide_stream<T><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, h->cfg.nz), dim3(64, 4), 0, s>>>(
+        p, fc, fn, psi, mask, cur);
+    if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
+    if (h->nb > 0) {
+        const int fbk = h->force_grid;
+        const dim3 gb(h->box_grid);
+        k_body_forces<T><<<dim3(fbk), b, 0, s>>>(p, par, st, fc, fn, psi, mask, cur, pforce);
+        k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB);
+        k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA);
+        k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB);
+        launch_kinetics<T>(h, p, par, st, next, sigma, phiB, phiA);
+        k_classify<T><<<gb, b, 0, s>>>(p, par, st, next, phiA, phiB, mask, 0, cpart);
+        k_convert_gather<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
+        k_post<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
+    }
+    if (ev) HIPCHK(h, hipEventRecord(ev[3], s));
     HIPCHK(h, hipGetLastError());
     ++h->steps;
     return PF_LBM_OK;
@@ -279,15 +309,16 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
                 const std::vector<BodyDev> &bodies, const StepState &st0) {
     const Prm<T> p = make_prm<T>(h);
     hipStream_t s = h->stream;
-    T *phiA = (T *)(h->ws + h->L.phiA), *phiB = (T *)(h->ws + h->L.phiB);
-    uint8_t *mask = (uint8_t *)(h->ws + h->L.mask);
+    double *phiA = (double *)(h->ws + h->L.phiA), *phiB = (double *)(h->ws + h->L.phiB);
+    cell_t *mask = (cell_t *)(h->ws + h->L.mask);
     double *tmp = (double *)(h->ws + h->L.fB);  // staging for FP64 host fields
     StepState *st = (StepState *)(h->ws + h->L.state);
     const dim3 b(256);
     const int gd = std::max(1, std::min(h->dense_blocks, 65535));
     (void)bodies_in;
-    HIPCHK(h, hipMemcpyAsync(h->ws + h->L.bodies, bodies.data(), sizeof(BodyDev) * std::max(h->nb, 1),
-                             hipMemcpyHostToDevice, s));
+    const size_t tab = sizeof(BodyDev) * std::max(h->nb, 1);
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->L.bodies, bodies.data(), tab, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->L.bodies + tab, bodies.data(), tab, hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(st, &st0, sizeof(StepState), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->ws + h->L.sigma, h->sigma.data(), sizeof(double) * h->sigma.size(),
                              hipMemcpyHostToDevice, s));
@@ -300,7 +331,12 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
         k_init_phi<T><<<gd, b, 0, s>>>(q, tmp, phiA + (size_t)a * h->Np, phiB + (size_t)a * h->Np);
         HIPCHK(h, hipStreamSynchronize(s));
     }
-    if (h->nb > 0) k_classify<T><<<dim3(h->box_blocks), b, 0, s>>>(p, 0, st, phiA, nullptr, mask, 1);
+    // solid / owner bits and the classification partials that the first step publishes
+    if (h->nb > 0) {
+        ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
+        k_classify<T><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, (const BodyDev *)(h->ws + h->L.bodies), phiA, nullptr,
+                                                        mask, 1, cpart);
+    }
     HIPCHK(h, hipMemcpyAsync(tmp, rho0, sizeof(double) * h->N, hipMemcpyHostToDevice, s));
     T *fA = fbuf<T>(h, 0), *fB = fbuf<T>(h, 1);
     // populations at rest into fA (reads the staged density in the fB area) ...
@@ -308,12 +344,8 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
     HIPCHK(h, hipStreamSynchronize(s));
     // ... then clear fB (solid nodes keep empty populations in both buffers)
     HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)19 * h->Np * sizeof(T), s));
-    HIPCHK(h, hipMemcpyAsync(st, &st0, sizeof(StepState), hipMemcpyHostToDevice, s));
-    // repulsion of the initial configuration feeds the first step's body update
-    if (h->nb > 1 && (h->cfg.flags & PF_LBM_REPULSION)) {
-        k_repulsion<T><<<dim3(h->box_blocks), b, 0, s>>>(p, 0, st, mask, (BodyDev *)(h->ws + h->L.bodies),
-                                                         (double *)(h->ws + h->L.prep));
-    }
+    // neighbour bits of the cell words
+    if (h->nb > 0) k_post<T><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
     return PF_LBM_OK;
@@ -352,7 +384,6 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
         if (!(bodies[a].mass_density > 0.0)) return fail(nullptr, PF_LBM_EINVAL, "body %d: mass_density must be > 0", a);
 
     const long long Np = (N + 63) / 64 * 64;
-    // box kernels: one block per ~2048 cells of the initial box, at most 1024 blocks
     std::vector<char> occ[3] = {std::vector<char>(cfg->nx, 0), std::vector<char>(cfg->ny, 0),
                                 std::vector<char>(cfg->nz, 0)};
     bool any = false;
@@ -378,14 +409,20 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
             if (hi - lo + 1 >= n[d]) {
                 lo = 0;
                 hi = n[d] - 1;
+            } else if (lo < 0) {  // lower corner in [0, n): unwrapped coordinates stay below 2 n
+                lo += n[d];
+                hi += n[d];
             }
             box[d] = lo;
             box[3 + d] = hi;
         }
     }
     const long long vol0 = any ? (long long)(box[3] - box[0] + 1) * (box[4] - box[1] + 1) * (box[5] - box[2] + 1) : 0;
-    const int box_blocks = (int)std::max(1LL, std::min(1024LL, (vol0 + 2047) / 2048));
-    const Layout L = make_layout(Np, n_bodies, cfg->precision, box_blocks);
+    // box kernels: about one thread per cell of the initial box with room to grow (grid-stride
+    // loops cover larger boxes), at most 4096 blocks
+    const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
+    const int box_grid = std::min(box_blocks, 2048), force_grid = std::min(box_blocks, 256);
+    const Layout L = make_layout(Np, n_bodies, cfg->precision, box_grid, force_grid);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
     if (!workspace) return PF_LBM_OK;
     if (!out) return fail(nullptr, PF_LBM_EINVAL, "out is NULL");
@@ -406,6 +443,8 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     h->Np = Np;
     h->dense_blocks = (int)((N + 255) / 256);
     h->box_blocks = box_blocks;
+    h->box_grid = box_grid;
+    h->force_grid = force_grid;
     const int np1 = n_bodies + 1;
     h->sigma.assign((size_t)np1 * np1, 0.0);
     for (int a = 0; a < np1; ++a)
@@ -431,10 +470,6 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     StepState st0;
     std::memset(&st0, 0, sizeof st0);
     for (int d = 0; d < 6; ++d) st0.box[0][d] = st0.box[1][d] = box[d];
-    for (int d = 0; d < 3; ++d) {
-        st0.tight[d] = INT32_MAX;
-        st0.tight[3 + d] = INT32_MIN;
-    }
     int rc = h->prec == PF_LBM_FP64 ? init_device<double>(h, bodies, rho0, phi0, bd, st0)
                                     : init_device<float>(h, bodies, rho0, phi0, bd, st0);
     if (rc != PF_LBM_OK) {
@@ -446,11 +481,61 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     return PF_LBM_OK;
 }
 
+namespace {
+
+int eager_step(pf_lbm *h) { return h->prec == PF_LBM_FP64 ? enqueue_step<double>(h) : enqueue_step<float>(h); }
+
+// capture an even/odd step pair on the handle's stream into an executable graph; on any failure
+// the handle keeps launching kernels one by one
+bool ensure_graph(pf_lbm *h) {
+    if (h->graph) return true;
+    if (h->graph_failed || !h->stream || (h->steps & 1)) return false;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph_failed = true;
+        return false;
+    }
+    const long long s0 = h->steps;
+    int rc = eager_step(h);
+    if (rc == PF_LBM_OK) rc = eager_step(h);
+    h->steps = s0;
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != PF_LBM_OK || e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        h->graph_failed = true;
+        return false;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph = nullptr;
+        h->graph_failed = true;
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
 int pf_lbm_step(pf_lbm *h, int32_t n_steps) {
     if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
     if (n_steps < 0) return fail(h, PF_LBM_EINVAL, "n_steps must be >= 0");
-    for (int k = 0; k < n_steps; ++k) {
-        const int rc = h->prec == PF_LBM_FP64 ? enqueue_step<double>(h) : enqueue_step<float>(h);
+    int n = n_steps;
+    if (n > 0 && (h->steps & 1)) {
+        const int rc = eager_step(h);
+        if (rc != PF_LBM_OK) return rc;
+        --n;
+    }
+    while (n >= 2 && !h->timing && ensure_graph(h)) {
+        HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
+        h->steps += 2;
+        n -= 2;
+    }
+    for (; n > 0; --n) {
+        const int rc = eager_step(h);
         if (rc != PF_LBM_OK) return rc;
     }
     return PF_LBM_OK;
@@ -460,7 +545,9 @@ int pf_lbm_forces(pf_lbm *h, double *F, double *T, double *X, double *V, double 
     if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
     std::vector<BodyDev> bd(std::max(h->nb, 1));
     StepState st;
-    HIPCHK(h, hipMemcpyAsync(bd.data(), h->ws + h->L.bodies, sizeof(BodyDev) * bd.size(), hipMemcpyDeviceToHost, h->stream));
+    const size_t tab = sizeof(BodyDev) * bd.size();
+    HIPCHK(h, hipMemcpyAsync(bd.data(), h->ws + h->L.bodies + (h->steps & 1) * tab, tab, hipMemcpyDeviceToHost,
+                             h->stream));
     HIPCHK(h, hipMemcpyAsync(&st, h->ws + h->L.state, sizeof st, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int a = 0; a < h->nb; ++a)
@@ -484,19 +571,19 @@ int pf_lbm_fields(pf_lbm *h, int32_t which, void *dst, int32_t dst_dtype) {
     if (dst_dtype != PF_LBM_DST_F64 && dst_dtype != PF_LBM_DST_F32) return fail(h, PF_LBM_EINVAL, "bad dst dtype");
     const int par = (int)(h->steps & 1);
     const dim3 g(std::max(1, std::min(h->dense_blocks, 65535))), b(256);
-    const uint8_t *mask = (const uint8_t *)(h->ws + h->L.mask);
+    const cell_t *mask = (const cell_t *)(h->ws + h->L.mask);
     if (h->prec == PF_LBM_FP64) {
         const Prm<double> p = make_prm<double>(h);
-        const double *f = fbuf<double>(h, par), *psi = (const double *)(h->ws + h->L.psi),
-                     *phi = (const double *)(h->ws + h->L.phiA);
+        const double *f = fbuf<double>(h, par), *psi = (const double *)(h->ws + h->L.psi);
+        const double *phi = (const double *)(h->ws + h->L.phiA);
         if (dst_dtype == PF_LBM_DST_F64)
             k_fields<double, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
         else
             k_fields<double, float><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
     } else {
         const Prm<float> p = make_prm<float>(h);
-        const float *f = fbuf<float>(h, par), *psi = (const float *)(h->ws + h->L.psi),
-                    *phi = (const float *)(h->ws + h->L.phiA);
+        const float *f = fbuf<float>(h, par), *psi = (const float *)(h->ws + h->L.psi);
+        const double *phi = (const double *)(h->ws + h->L.phiA);
         if (dst_dtype == PF_LBM_DST_F64)
             k_fields<float, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
         else
@@ -518,7 +605,38 @@ int pf_lbm_diagnostics(pf_lbm *h, double *out4) {
     return PF_LBM_OK;
 }
 
-void pf_lbm_destroy(pf_lbm *h) { delete h; }
+int pf_lbm_timing(pf_lbm *h, int32_t enable, double *out4) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    if (enable) {
+        h->timing = true;
+        h->timed = 0;
+        return PF_LBM_OK;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double kern = 0.0, step = 0.0;
+    for (int k = 0; k < h->timed; ++k) {
+        float a = 0.f, b = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&a, h->ev[4 * k + 1], h->ev[4 * k + 2]));
+        HIPCHK(h, hipEventElapsedTime(&b, h->ev[4 * k + 0], h->ev[4 * k + 3]));
+        kern += a;
+        step += b;
+    }
+    if (out4) {
+        out4[0] = h->timed;
+        out4[1] = h->timed ? kern / h->timed : 0.0;
+        out4[2] = h->timed ? step / h->timed : 0.0;
+        out4[3] = 0.0;
+    }
+    h->timing = false;
+    return PF_LBM_OK;
+}
+
+void pf_lbm_destroy(pf_lbm *h) {
+    if (!h) return;
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+}
 
 const char *pf_lbm_last_error(const pf_lbm *h) { return h ? h->err.c_str() : g_init_error.c_str(); }
 

@@ -61,7 +61,8 @@ class Simulation:
         self.nb = len(bodies)
         self.shape = tuple(int(v) for v in (params["nz"], params["ny"], params["nx"]))
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the library captures its step into a HIP graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         cfg, sig = make_config(params, self.nb, precision)
         barr = make_bodies(bodies)
         r = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
@@ -70,6 +71,7 @@ class Simulation:
         if rc != B.PF_LBM_OK:
             raise PfLbmError(rc, B.pf_lbm_last_error(None))
         self.workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
         self.ws_bytes = need
         rc, h, _ = B.pf_lbm_init(cfg, self.nb, barr, r, p, self.workspace.data_ptr(), need, self.stream.cuda_stream)
         if rc != B.PF_LBM_OK:
@@ -102,6 +104,7 @@ class Simulation:
         out = torch.empty(self.shape, dtype=dtype, device=self.device)
         dt = B.PF_LBM_DST_F64 if dtype == torch.float64 else B.PF_LBM_DST_F32
         self._check(B.pf_lbm_fields(self._h, which, out.data_ptr(), dt))
+        self.stream.synchronize()  # the output is written on the library's stream
         return out
 
     def rho(self) -> np.ndarray:
@@ -117,6 +120,11 @@ class Simulation:
 
     def mask(self):
         return (self.field("solid").cpu().numpy().astype(np.int32), self.field("owner").cpu().numpy().astype(np.int32))
+
+    def timing(self, enable: bool):
+        rc, out = B.pf_lbm_timing(self._h, 1 if enable else 0)
+        self._check(rc)
+        return {"steps": int(out[0]), "kernel_ms": out[1], "step_ms": out[2]}
 
     def diag(self) -> dict:
         rc, out = B.pf_lbm_diagnostics(self._h)
