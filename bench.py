@@ -42,18 +42,36 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+MASK_BYTES = 4  # one 32-bit cell word per node
+
+
 def step_bytes_per_cell(real: int) -> float:
     """Algorithmic bytes of one coupled step per node: 19 populations read and written, the
-    pseudopotential written once and read once, the mask read once (phase-field work on the
-    interface band is below 1 %)."""
-    return 2 * 19 * real + 2 * real + 1
+    pseudopotential written once and read once, the cell word read once (the phase-field work on
+    the box around the bodies is not counted)."""
+    return 2 * 19 * real + 2 * real + MASK_BYTES
 
 
 def kernel_bytes(n_fluid: int, n_solid: int, real: int) -> float:
     """Algorithmic bytes of one collide-stream launch: a fluid node reads and writes its 19
-    populations and reads its own pseudopotential and mask byte (neighbour values are re-reads
-    of the same arrays); a solid node reads its mask byte only."""
-    return n_fluid * (2 * 19 * real + real + 1) + n_solid * 1.0
+    populations and reads its own pseudopotential and cell word (neighbour values are re-reads
+    of the same arrays); a solid node reads its cell word only."""
+    return n_fluid * (2 * 19 * real + real + MASK_BYTES) + n_solid * float(MASK_BYTES)
+
+
+def copy_calibration(mib: int, reps: int) -> int:
+    """Plain device-to-device copies of a known size, for scaling the HBM byte counters of a
+    profiler run (FETCH_SIZE / WRITE_SIZE per dispatch against the bytes actually moved)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "dispatches": reps}), flush=True)
+    return 0
 
 
 def traffic_from_profile(workload: str, precision: str, sha: str):
@@ -94,7 +112,11 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain copies of MIB MiB (profiler counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration, 5)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -144,6 +166,7 @@ def main() -> int:
                 "kernel_ms": round(tm["kernel_ms"], 5), "bytes_per_launch": kb}
     b = sim.bodies()
     ok = all(math.isfinite(v) for v in np.asarray(b["F"]).ravel())
+    d = sim.diag()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -159,6 +182,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "finite_forces": ok,
+        "node_conversions": {"steps": d["step"], "fluid_to_solid": d["n_f2s"], "solid_to_fluid": d["n_s2f"]},
         "source_sha": sha,
     }
     print(json.dumps(out), flush=True)

@@ -220,56 +220,78 @@ __device__ __forceinline__ int wrap2(int i, int n) {
     return i;
 }
 
-// Run by one whole wave at the start of a step: combine the per-block reclassification results
-// of the previous step in a fixed order and publish
-//  * this step's box: phase-field support + 3-cell margin, the whole axis once it would wrap onto
-//    itself, lower corner brought into [0, n) (so unwrapped coordinates stay below 2 n);
-//  * the per-body solid radii (bound the repulsion search);
-//  * the volume driving term of each body, h_a = (4 eta / pi^2) (V_ref - sum phi_a) /
-//    #{floor < phi_a < 1} (Sec. 3.3; 0 without interface nodes), into the body table;
-// and clear the event flag for this step's reclassification.
-__device__ __forceinline__ void publish_step_state(int parity, int nx, int ny, int nz, int nb, double eta,
+// Run by the 4 waves of one block at the start of a step: combine the per-block
+// reclassification results of the previous step in a fixed order and publish
+//  * this step's box (wave 0): phase-field support + 3-cell margin, the whole axis once it would
+//    wrap onto itself, lower corner brought into [0, n) (so unwrapped coordinates stay below 2 n);
+//  * per body (wave 1 + b % 3): the solid radius (bounds the repulsion search) and the volume
+//    driving term h_a = (4 eta / pi^2) (V_ref - sum phi_a) / #{floor < phi_a < 1} (Sec. 3.3; 0
+//    without interface nodes), into the body table;
+// and clear the event flag for this step's reclassification.  Each lane sums its parts with four
+// independent accumulators, then a fixed xor-shuffle tree combines the lanes.
+__device__ __forceinline__ void publish_step_state(int wave, int parity, int nx, int ny, int nz, int nb, double eta,
                                                    StepState *st, BodyDev *bodies, const ClassifyPart *cpart,
                                                    int nblk) {
     const int lane = (int)(threadIdx.x & 63);
-    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
-    for (int j = lane; j < nblk; j += 64)
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = min(lo[d], cpart[j].lo[d]);
-            hi[d] = max(hi[d], cpart[j].hi[d]);
-        }
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = wave_min(lo[d]);
-        hi[d] = wave_max(hi[d]);
-    }
-    if (lane == 0) {
-        const int n[3] = {nx, ny, nz};
-        const bool empty = lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2];
-        for (int d = 0; d < 3; ++d) {
-            int l = lo[d] - 3, h = hi[d] + 3;
-            if (h - l + 1 >= n[d]) {
-                l = 0;
-                h = n[d] - 1;
-            } else {
-                const int s = wrap2(l, n[d]) - l;
-                l += s;
-                h += s;
+    if (wave == 0) {
+        int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+        for (int j = lane; j < nblk; j += 64)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = min(lo[d], cpart[j].lo[d]);
+                hi[d] = max(hi[d], cpart[j].hi[d]);
             }
-            st->box[parity][d] = empty ? 0 : l;
-            st->box[parity][3 + d] = empty ? -1 : h;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = wave_min(lo[d]);
+            hi[d] = wave_max(hi[d]);
         }
-        st->events = 0u;
+        if (lane == 0) {
+            const int n[3] = {nx, ny, nz};
+            const bool empty = lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2];
+            for (int d = 0; d < 3; ++d) {
+                int l = lo[d] - 3, h = hi[d] + 3;
+                if (h - l + 1 >= n[d]) {
+                    l = 0;
+                    h = n[d] - 1;
+                } else {
+                    const int s = wrap2(l, n[d]) - l;
+                    l += s;
+                    h += s;
+                }
+                st->box[parity][d] = empty ? 0 : l;
+                st->box[parity][3 + d] = empty ? -1 : h;
+            }
+            st->events = 0u;
+        }
+        return;
     }
     const double PI = 3.14159265358979323846;
-    for (int b = 0; b < nb; ++b) {
-        float r = 0.0f;
-        double v = 0.0;
-        int c = 0;
-        for (int j = lane; j < nblk; j += 64) {
-            r = fmaxf(r, cpart[j].srad[b]);
-            v += cpart[j].vol[b];
-            c += (int)cpart[j].icnt[b];
+    for (int b = wave - 1; b < nb; b += 3) {
+        float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f, r3 = 0.0f;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+        int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        int j = lane;
+        for (; j + 192 < nblk; j += 256) {
+            r0 = fmaxf(r0, cpart[j].srad[b]);
+            r1 = fmaxf(r1, cpart[j + 64].srad[b]);
+            r2 = fmaxf(r2, cpart[j + 128].srad[b]);
+            r3 = fmaxf(r3, cpart[j + 192].srad[b]);
+            v0 += cpart[j].vol[b];
+            v1 += cpart[j + 64].vol[b];
+            v2 += cpart[j + 128].vol[b];
+            v3 += cpart[j + 192].vol[b];
+            c0 += (int)cpart[j].icnt[b];
+            c1 += (int)cpart[j + 64].icnt[b];
+            c2 += (int)cpart[j + 128].icnt[b];
+            c3 += (int)cpart[j + 192].icnt[b];
         }
+        for (; j < nblk; j += 64) {
+            r0 = fmaxf(r0, cpart[j].srad[b]);
+            v0 += cpart[j].vol[b];
+            c0 += (int)cpart[j].icnt[b];
+        }
+        float r = fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+        double v = (v0 + v1) + (v2 + v3);
+        int c = (c0 + c1) + (c2 + c3);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
         v = wave_sum(v);

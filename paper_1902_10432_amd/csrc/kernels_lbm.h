@@ -7,29 +7,22 @@
 namespace pfl {
 
 // Pseudopotential psi = 1 - exp(-rho/rho0) of every fluid node; a solid node carries the value
-// of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.  With bodies, the
-// first wave of the first block also publishes the step's box, solid radii, volume terms and
-// event flag from the previous reclassification (publish_step_state): that short reduction hides
-// behind the dense pass instead of costing a launch of its own.
+// of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.
 template <typename T>
-__global__ __launch_bounds__(256) void k_psi(Prm<T> p, int parity, const T *__restrict__ f,
-                                             const cell_t *__restrict__ mask, BodyDev *bodies, T *__restrict__ psi,
-                                             StepState *st, const ClassifyPart *__restrict__ cpart, int cblk) {
+__global__ __launch_bounds__(256) void k_psi(Prm<T> p, const T *__restrict__ f, const cell_t *__restrict__ mask,
+                                             const BodyDev *__restrict__ bodies, T *__restrict__ psi) {
     const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    if (idx < p.N) {  // flat 1-D launch: no neighbours needed
-        const cell_t m = mask[idx];
-        T out;
-        if (m & C_SOLID) {
-            out = (T)bodies[owner_of(m)].psi_s;
-        } else {
-            T r = T(0);
-            sfor<19>([&](auto I) { r += f[(long long)I * p.Np + idx]; });
-            out = -expm1(-r * p.inv_rho0);
-        }
-        psi[idx] = out;
+    if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed
+    const cell_t m = mask[idx];
+    T out;
+    if (m & C_SOLID) {
+        out = (T)bodies[owner_of(m)].psi_s;
+    } else {
+        T r = T(0);
+        sfor<19>([&](auto I) { r += f[(long long)I * p.Np + idx]; });
+        out = -expm1(-r * p.inv_rho0);
     }
-    if (cpart && blockIdx.x == 0 && threadIdx.x < 64)
-        publish_step_state(parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart, cblk);
+    psi[idx] = out;
 }
 
 // periodic neighbour offsets of one cell as unsigned index deltas (the sum with the cell index
@@ -77,6 +70,11 @@ struct Nbr {
         return (Dir<I>::x == 1 ? xp : (Dir<I>::x == -1 ? xm : 0)) + (Dir<I>::y == 1 ? yp : (Dir<I>::y == -1 ? ym : 0)) +
                (Dir<I>::z == 1 ? zp : (Dir<I>::z == -1 ? zm : 0));
     }
+    // the same for a direction known only at run time
+    __device__ __forceinline__ int off_rt(int i) const {
+        const int cx = kCX[i], cy = kCY[i], cz = kCZ[i];
+        return (cx > 0 ? xp : (cx < 0 ? xm : 0)) + (cy > 0 ? yp : (cy < 0 ? ym : 0)) + (cz > 0 ? zp : (cz < 0 ? zm : 0));
+    }
 };
 
 // Rigid-body velocity V + omega x (p - X) at point p (minimum image), Sec. 3.1.1.
@@ -114,6 +112,10 @@ __device__ __forceinline__ bool cell_of_block(int nx, int ny, int &x, int &y, in
 // moving-wall term when the neighbour is solid.  The wall terms are taken back from the rest
 // population (Sec. 3.2.1, 3.2.2, 3.2.3).  Solid nodes are skipped and receive nothing.
 //
+// With bodies, the first block also publishes the step's box, solid radii, volume terms and event
+// flag from the previous reclassification (publish_step_state) before its own cells: that short
+// reduction chain then hides behind the longest pass of the step instead of costing a launch.
+//
 // Arithmetic is organised by opposite pairs (c_opp = -c): with cu = c.v, cF = c.F,
 //   f*_i = (1 - 1/tau) f_i + w (even + odd),  f*_opp = (1 - 1/tau) f_opp + w (even - odd),
 //   even = rho/tau (1 - 3/2 v.v) - 3 g v.F + 9/2 rho/tau cu^2 + 9 g cu cF,  odd = 3 rho/tau cu + 3 g cF,
@@ -121,7 +123,10 @@ __device__ __forceinline__ bool cell_of_block(int nx, int ny, int &x, int &y, in
 template <typename T>
 __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__restrict__ fin, T *__restrict__ fout,
                                                         const T *__restrict__ psi, const cell_t *__restrict__ mask,
-                                                        const BodyDev *__restrict__ bodies) {
+                                                        BodyDev *bodies, int parity, StepState *st,
+                                                        const ClassifyPart *__restrict__ cpart, int cblk) {
+    if (cpart && (blockIdx.x | blockIdx.y | blockIdx.z) == 0)
+        publish_step_state((int)threadIdx.y, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart, cblk);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     int x, y, z;
     if (!cell_of_block(nx, ny, x, y, z)) return;
@@ -237,28 +242,46 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__res
 // per touched body (64-lane shuffles) into LDS in a fixed order and every block writes FP64
 // partials [body * 6 + component][block], summed by the first advection sweep (k_advect), which
 // also advances the bodies.
+// waves per block of the force scan (one block per CU), sized so that the gathered link values
+// stay in registers: 12 in FP32, 8 in FP64
 template <typename T>
-__global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, const StepState *st,
+constexpr int force_waves() {
+    return sizeof(T) == 4 ? 12 : 8;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * force_waves<T>()) void k_body_forces(Prm<T> p, int parity, const StepState *st,
                                                      const T *__restrict__ fin, const T *__restrict__ fpost,
                                                      const T *__restrict__ psi, const cell_t *__restrict__ mask,
                                                      const BodyDev *__restrict__ bodies, double *part) {
-    __shared__ double acc[4][PF_LBM_MAX_BODIES][6];
+    constexpr int W = force_waves<T>(), NT = 64 * W;
+    __shared__ double acc[W][PF_LBM_MAX_BODIES][6];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nbod = p.nb;
-    for (int k = tid; k < 4 * PF_LBM_MAX_BODIES * 6; k += 256) (&acc[0][0][0])[k] = 0.0;
+    __shared__ double mag_tab[49];  // repulsion magnitude by squared distance (|d| <= 4 per axis)
+    for (int k = tid; k < W * PF_LBM_MAX_BODIES * 6; k += NT) (&acc[0][0][0])[k] = 0.0;
+    if (tid < 49) {
+        const double r = sqrt((double)tid);
+        mag_tab[tid] = tid > 0 && r < p.r_c ? p.e0 * (p.n_exp / p.r_c) * pow(fabs((r - p.r_c) / p.r_c), p.n_exp - 1.0) : 0.0;
+    }
     __syncthreads();
     const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
     const bool rep = nbod > 1 && (p.flags & PF_LBM_REPULSION);
-    const double rc = p.r_c, ne = p.n_exp, e0 = p.e0;
+    const double rc = p.r_c;
     const int R = rep ? (int)ceil(rc) : 0;
-    for (int base = blockIdx.x * 256; base < it.vol; base += gridDim.x * 256) {
+    for (int base = blockIdx.x * NT; base < it.vol; base += gridDim.x * NT) {
         const int k = base + tid;
         uint32_t touched = 0;
         int x = 0, y = 0, z = 0, idx = 0, b1 = -1;
+        uint32_t nbits = 0;  // solid-neighbour bits of a fluid node
         bool fluid = false;
         T rho = T(0), ps0 = T(0);
+        // per link i into a solid neighbour: its owner (4-bit fields) and the body-independent part
+        // of the link force, a_i = 2 f_opp(i) + G psi(x) w_i psi(x + c_i)
+        uint32_t own[3] = {0u, 0u, 0u};
+        T a[19];
         if (k < it.vol) {
             int u[3], c[3];
             it.cell(k, u, c);
@@ -269,18 +292,28 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, const
             const cell_t w0 = mask[idx];
             if (!(w0 & C_SOLID)) {
                 fluid = true;
-                if (w0 & C_NBMASK) {
-                    const Nbr nb(x, y, z, nx, ny, nz);
+                nbits = w0 & C_NBMASK;
+                if (nbits) {
+                    // one round of independent gathers (byte offsets from uniform bases)
+                    const NbrU ne(x, y, z, nx, ny, nz, 1);
+                    const uint32_t ib = (uint32_t)idx * (uint32_t)sizeof(T);
+                    sfor<19>([&](auto I) { rho += ldb(fin + (long long)I * Np, ib); });
+                    ps0 = ldb(psi, ib);
+                    const T gp = p.G * ps0;
                     sfor<19>([&](auto I) {
                         constexpr int i = decltype(I)::value;
+                        a[i] = T(0);
                         if constexpr (i > 0) {
-                            if (w0 & (1u << i)) touched |= 1u << owner_of(mask[idx + nb.template off<i>()]);
+                            if (nbits & (1u << i)) {
+                                const uint32_t n = ne.template at<i>((uint32_t)idx);
+                                const uint32_t o = (uint32_t)owner_of(ldb(mask, n * 4u));
+                                own[i >> 3] |= o << (4 * (i & 7));
+                                touched |= 1u << o;
+                                a[i] = T(2) * ldb(fpost + (long long)Dir<i>::opp * Np, ib) +
+                                       gp * Dir<i>::template w<T>() * ldb(psi, n * (uint32_t)sizeof(T));
+                            }
                         }
                     });
-                    if (touched) {
-                        sfor<19>([&](auto I) { rho += fin[(long long)I * Np + idx]; });
-                        ps0 = psi[idx];
-                    }
                 }
             } else if (rep) {
                 b1 = owner_of(w0);
@@ -309,23 +342,19 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, const
             wt &= wt - 1;
             double v[6] = {0, 0, 0, 0, 0, 0};
             if ((touched & (1u << b)) && fluid) {
-                const Nbr nb(x, y, z, nx, ny, nz);
                 const BodyDev &B = bodies[b];
                 sfor<19>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     if constexpr (i > 0) {
-                        const int n = idx + nb.template off<i>();
-                        const cell_t mn = mask[n];
-                        if ((mn & C_SOLID) && owner_of(mn) == b) {
+                        if ((nbits & (1u << i)) && ((own[i >> 3] >> (4 * (i & 7))) & 15u) == (uint32_t)b) {
                             const double px = x + 0.5 * Dir<i>::x, py = y + 0.5 * Dir<i>::y, pz = z + 0.5 * Dir<i>::z;
                             double uwx, uwy, uwz;
                             wall_velocity(p, B, px, py, pz, uwx, uwy, uwz);
                             const double cuw = Dir<i>::x * uwx + Dir<i>::y * uwy + Dir<i>::z * uwz;
+                            // moving-wall term g; the link carries 2 f*_i + g = 2 f_opp(i) - g to the
+                            // body plus the pseudopotential reaction, both along c_i
                             const T g = T(-6.0 * Dir<i>::template w<double>() * cuw) * rho;
-                            const T fr = fpost[(long long)Dir<i>::opp * Np + idx];
-                            // momentum to the body + pseudopotential reaction, both along c_i
-                            const double s = (double)(T(2) * fr - g) +
-                                             (double)(p.G * ps0 * Dir<i>::template w<T>() * psi[n]);
+                            const double s = (double)(a[i] - g);
                             const double fx = s * Dir<i>::x, fy = s * Dir<i>::y, fz = s * Dir<i>::z;
                             const double rx = mimg_r(px - B.X[0], nx, p.inv_n[0]), ry = mimg_r(py - B.X[1], ny, p.inv_n[1]),
                                          rz = mimg_r(pz - B.X[2], nz, p.inv_n[2]);
@@ -349,7 +378,7 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, const
                             const int b2 = owner_of(mq);
                             if (b2 <= b1 || (b != b1 && b != b2)) continue;
                             const double r = sqrt((double)d2);
-                            const double mag = e0 * (ne / rc) * pow(fabs((r - rc) / rc), ne - 1.0);
+                            const double mag = mag_tab[d2];
                             // force on b1 at p, directed from q to p
                             double fx = -dx / r * mag, fy = -dy / r * mag, fz = -dz / r * mag;
                             double ax = x, ay = y, az = z;
@@ -379,9 +408,11 @@ __global__ __launch_bounds__(256) void k_body_forces(Prm<T> p, int parity, const
         }
     }
     __syncthreads();
-    for (int k = tid; k < nbod * 6; k += 256) {
+    for (int k = tid; k < nbod * 6; k += NT) {
         const int b = k / 6, c = k % 6;
-        part[(long long)k * gridDim.x + blockIdx.x] = ((acc[0][b][c] + acc[1][b][c]) + acc[2][b][c]) + acc[3][b][c];
+        double s = 0.0;
+        for (int w = 0; w < W; ++w) s += acc[w][b][c];
+        part[(long long)k * gridDim.x + blockIdx.x] = s;
     }
 }
 

@@ -281,15 +281,15 @@ int enqueue_step(pf_lbm *h) {
         ++h->timed;
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
-    k_psi<T><<<gd, b, 0, s>>>(p, par, fc, mask, cur, psi, st, h->nb > 0 ? cpart : nullptr, h->box_grid);
+    k_psi<T><<<gd, b, 0, s>>>(p, fc, mask, cur, psi);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
     k_collide_stream<T><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, h->cfg.nz), dim3(64, 4), 0, s>>>(
-        p, fc, fn, psi, mask, cur);
+        p, fc, fn, psi, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->box_grid);
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
         const dim3 gb(h->box_grid);
-        k_body_forces<T><<<dim3(fbk), b, 0, s>>>(p, par, st, fc, fn, psi, mask, cur, pforce);
+        k_body_forces<T><<<dim3(fbk), dim3(64 * force_waves<T>()), 0, s>>>(p, par, st, fc, fn, psi, mask, cur, pforce);
         k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB);
         k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA);
         k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB);
@@ -421,7 +421,7 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     // box kernels: about one thread per cell of the initial box with room to grow (grid-stride
     // loops cover larger boxes), at most 4096 blocks
     const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
-    const int box_grid = std::min(box_blocks, 2048), force_grid = std::min(box_blocks, 256);
+    const int box_grid = std::min(box_blocks, 2048), force_grid = std::min((box_blocks + 3) / 4, 256);
     const Layout L = make_layout(Np, n_bodies, cfg->precision, box_grid, force_grid);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
     if (!workspace) return PF_LBM_OK;
