@@ -29,14 +29,26 @@ PLATE_DENSITY_RATIO = 1.72e4   # rho_S / rho_L for the plate tests (Sec. 4.2)
 SPHERE_DENSITY = 4.0           # sphere mass density (Sec. 4.3)
 
 
-def wetting_rho_for_angle(theta_deg: float, G: float = -5.0, rho0: float = 1.0) -> float:
-    """Wetting parameter varrho_B for a target contact angle.
+# Wetting parameter varrho_B against contact angle (degrees) at G = -5, rho0 = 1, tau = 1,
+# measured with the oracle on the planar capillary bridge through the Young-Laplace law
+# (tests/golden/calibrate_wetting.py writes tests/golden/wetting_calibration.json).
+WETTING_TABLE = ((0.0, 1.3542), (30.0, 1.2280), (60.0, 0.9690), (90.0, 0.7067))
 
-    Provisional map (the paper defers the relation to Benzi et al. 2006): neutral wetting at the
-    mean of the coexistence densities, linear in cos(theta) up to the liquid density."""
-    rv, rl = coexistence_densities(G, rho0)
-    mid = 0.5 * (rv + rl)
-    return mid + (rl - mid) * math.cos(math.radians(theta_deg))
+
+def wetting_rho_for_angle(theta_deg: float, G: float = -5.0, rho0: float = 1.0) -> float:
+    """Wetting parameter varrho_B for a contact angle in [0, 90] degrees: the calibrated table,
+    linear in cos(theta) between its points (the paper defers this map to Benzi et al. 2006).
+    The table holds for G = -5, rho0 = 1 only."""
+    if G != -5.0 or rho0 != 1.0:
+        raise ValueError("the wetting table is calibrated for G = -5, rho0 = 1")
+    if not 0.0 <= theta_deg <= 90.0:
+        raise ValueError("contact angles in [0, 90] degrees only")
+    c = math.cos(math.radians(theta_deg))
+    pts = [(math.cos(math.radians(t)), w) for t, w in WETTING_TABLE]
+    for (c0, w0), (c1, w1) in zip(pts, pts[1:]):
+        if c1 <= c <= c0:
+            return w0 + (w1 - w0) * (c - c0) / (c1 - c0)
+    return pts[-1][1]
 
 
 @dataclass
@@ -116,6 +128,36 @@ def plates_bridge(n: int = 32, radius: float = 6.0, gap: int = 8, plate: int = 1
     meta = {"radius": radius, "gap": gap, "rho_l": rl, "rho_v": rv, "theta_deg": theta_deg,
             "plate_cells": plate * plate * thickness, "z_faces": (z_bot_hi + 0.5, z_top_lo - 0.5)}
     return Workload("plates_bridge", p, bodies, rho, phis, meta)
+
+
+def planar_bridge(nx: int = 80, nz: int = 50, gap: int = 20, plate: int = 48, thickness: int = 2,
+                  liquid_width: float = 28.0, width: float = 4.0, wetting_rho: float | None = None,
+                  theta_deg: float = 90.0, **over) -> Workload:
+    """Planar capillary bridge (Sec. 2.1.1, planar case): two finite plates, ``plate`` cells long
+    in x and infinite in y (ny = 1), solid faces ``gap`` cells apart, joined by a liquid slab
+    ``liquid_width`` cells wide; vapour all around.  The plates are held fixed."""
+    shape = (nz, 1, nx)
+    rv, rl = coexistence_densities()
+    x, y, z = grid(shape)
+    zc, xc = nz / 2.0 - 0.5, nx / 2.0 - 0.5
+    z_bot_hi = int(round(zc - gap / 2.0 - 0.5))
+    z_top_lo = int(round(zc + gap / 2.0 + 0.5))
+    x0 = int(round(xc - plate / 2.0 + 0.5))
+    x1 = x0 + plate - 1
+    phis = np.stack([
+        plate_phi(shape, (x0, 0, z_bot_hi - thickness + 1), (x1, 0, z_bot_hi), width),
+        plate_phi(shape, (x0, 0, z_top_lo), (x1, 0, z_top_lo + thickness - 1), width),
+    ])
+    d = np.maximum(np.abs(x - xc) - liquid_width / 2.0, np.abs(z - zc) - gap / 2.0)
+    rho = liquid_density(d, rl, rv, width)
+    wet = wetting_rho_for_angle(theta_deg) if wetting_rho is None else float(wetting_rho)
+    ms = PLATE_DENSITY_RATIO * rl
+    bodies = [_body(ms, wet, fixed=1), _body(ms, wet, fixed=1)]
+    over.setdefault("motion", 0)
+    p = default_params(nx, 1, nz, 2, **over)
+    meta = {"gap": gap, "rho_l": rl, "rho_v": rv, "wetting_rho": wet, "z_mid": int(round(zc)),
+            "x_centre": int(round(xc)), "z_faces": (z_bot_hi + 0.5, z_top_lo - 0.5)}
+    return Workload("planar_bridge", p, bodies, rho, phis, meta)
 
 
 def two_spheres_bridge(n: int = 128, radius: float = 20.0, gap: float = 4.0, liquid_fraction: float = 0.02,
@@ -216,6 +258,7 @@ def tiny_moving_body(shape=(10, 12, 14), radius: float = 3.2, v=(0.05, -0.03, 0.
 
 
 WORKLOADS = {
+    "planar_bridge": planar_bridge,
     "plates_bridge": plates_bridge,
     "two_spheres_bridge": two_spheres_bridge,
     "tetrahedron_drop": tetrahedron_drop,
