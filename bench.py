@@ -45,18 +45,22 @@ def source_sha() -> str:
 MASK_BYTES = 4  # one 32-bit cell word per node
 
 
-def step_bytes_per_cell(real: int) -> float:
+# bytes per stored population and per pseudopotential value of each precision form
+FORMS = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4)}
+
+
+def step_bytes_per_cell(pop: int, arith: int) -> float:
     """Algorithmic bytes of one coupled step per node: 19 populations read and written, the
     pseudopotential written once and read once, the cell word read once (the phase-field work on
     the box around the bodies is not counted)."""
-    return 2 * 19 * real + 2 * real + MASK_BYTES
+    return 2 * 19 * pop + 2 * arith + MASK_BYTES
 
 
-def kernel_bytes(n_fluid: int, n_solid: int, real: int) -> float:
+def kernel_bytes(n_fluid: int, n_solid: int, pop: int, arith: int) -> float:
     """Algorithmic bytes of one collide-stream launch: a fluid node reads and writes its 19
     populations and reads its own pseudopotential and cell word (neighbour values are re-reads
     of the same arrays); a solid node reads its cell word only."""
-    return n_fluid * (2 * 19 * real + real + MASK_BYTES) + n_solid * float(MASK_BYTES)
+    return n_fluid * (2 * 19 * pop + arith + MASK_BYTES) + n_solid * float(MASK_BYTES)
 
 
 def copy_calibration(mib: int, reps: int) -> int:
@@ -109,9 +113,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="two_spheres_bridge")
     ap.add_argument("--n", type=int, default=None, help="grid size override (cubic)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16-storage comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     args = ap.parse_args()
@@ -130,7 +135,7 @@ def main() -> int:
 
     kw = {"n": args.n} if args.n else {}
     w = make_workload(args.workload, **kw)
-    real = 4 if args.precision == "fp32" else 8
+    pop, arith = FORMS[args.precision]
     log(f"workload {w.name} {w.shape} bodies={len(w.bodies)} {args.precision}")
     sim = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=args.precision)
     stream = sim.stream
@@ -147,7 +152,7 @@ def main() -> int:
     ms = start.elapsed_time(end)
     ms_per_step = ms / args.steps
     mlups = w.cells * args.steps / (ms / 1e3) / 1e6
-    pct_step = mlups * 1e6 * step_bytes_per_cell(real) / (HBM_PEAK_GBS * 1e9)
+    pct_step = mlups * 1e6 * step_bytes_per_cell(pop, arith) / (HBM_PEAK_GBS * 1e9)
     log(f"timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), {mlups:.1f} MLUPS")
 
     # dominant kernel: mean launch time from events recorded around it on the library's stream
@@ -157,7 +162,7 @@ def main() -> int:
     solid = sim.field("solid").sum().item()
     n_solid = int(solid)
     n_fluid = w.cells - n_solid
-    kb = kernel_bytes(n_fluid, n_solid, real)
+    kb = kernel_bytes(n_fluid, n_solid, pop, arith)
     achieved = kb / (tm["kernel_ms"] / 1e3) / 1e9
     sha = source_sha()
     traffic = traffic_from_profile(w.name, args.precision, sha)
@@ -168,6 +173,29 @@ def main() -> int:
     ok = all(math.isfinite(v) for v in np.asarray(b["F"]).ravel())
     d = sim.diag()
 
+    # the FP16-storage form on the same workload, timed the same way (its force error against
+    # the FP64 oracle is checked by the GPU tests: <= 1e-3 relative)
+    forms = None
+    if args.precision == "fp32" and not args.no_forms:
+        del sim
+        torch.cuda.empty_cache()
+        h = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision="fp16")
+        h.step(args.warmup)
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(h.stream)
+        h.step(args.steps)
+        s1.record(h.stream)
+        torch.cuda.synchronize()
+        hms = s0.elapsed_time(s1)
+        hm = w.cells * args.steps / (hms / 1e3) / 1e6
+        forms = {"fp16_store": {"value": round(hm, 2), "unit": "MLUPS", "ms_per_step": round(hms / args.steps, 5),
+                                "vs_fp32": round(hm / mlups, 3),
+                                "pct_hbm_step_algorithmic": round(hm * 1e6 * step_bytes_per_cell(*FORMS["fp16"])
+                                                                  / (HBM_PEAK_GBS * 1e9), 4)}}
+        log(f"fp16 storage: {hm:.1f} MLUPS ({hm / mlups:.2f}x fp32)")
+        del h
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -175,12 +203,13 @@ def main() -> int:
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real == 4 else "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16-store/f32"}[args.precision], "data": "synthetic",
         "config": {"workload": f"{w.name} {w.shape[2]}x{w.shape[1]}x{w.shape[0]} D3Q19, {len(w.bodies)} bodies, "
                                f"motion+kinetics on", "cells": w.cells, "precision": args.precision},
         "pct_hbm_step_algorithmic": round(pct_step, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
         "finite_forces": ok,
         "node_conversions": {"steps": d["step"], "fluid_to_solid": d["n_f2s"], "solid_to_fluid": d["n_s2f"]},
         "source_sha": sha,

@@ -51,8 +51,13 @@ enum {
 
 enum { PF_LBM_D3Q19 = 19 };
 
-/* arithmetic / storage of the fluid populations and phase fields */
-enum { PF_LBM_FP64 = 0, PF_LBM_FP32 = 1 };
+/* Arithmetic and storage of the fluid populations.  FP64 and FP32 store and compute in that
+ * type.  FP16_STORE stores each population f_i(x) as an FP16 deviation from its equilibrium
+ * weight at rest, f_i - w_i rho~(x), with rho~(x) = -rho0 log(1 - psi(x)) from the node's
+ * pseudopotential of the previous step (its density, up to FP32 rounding), and computes in FP32.
+ * In every form the phase fields are FP64, and the per-body force and torque sums, the mass
+ * checks and the rigid-body update are FP64. */
+enum { PF_LBM_FP64 = 0, PF_LBM_FP32 = 1, PF_LBM_FP16_STORE = 2 };
 
 /* step options (config.flags) */
 enum {
@@ -80,7 +85,7 @@ typedef struct {
     uint32_t struct_size;   /* sizeof(pf_lbm_config): ABI check                                  */
     int32_t nx, ny, nz;     /* periodic box, cells per axis (each >= 1)                          */
     int32_t lattice;        /* PF_LBM_D3Q19                                                       */
-    int32_t precision;      /* PF_LBM_FP64 or PF_LBM_FP32                                         */
+    int32_t precision;      /* PF_LBM_FP64, PF_LBM_FP32 or PF_LBM_FP16_STORE                      */
     int32_t flags;          /* PF_LBM_KINETICS | PF_LBM_MOTION | PF_LBM_REPULSION                 */
     double tau;             /* BGK relaxation time, > 1/2 (Sec. 3.2.1)                            */
     double G;               /* pseudopotential coupling (Sec. 3.2.3)                              */

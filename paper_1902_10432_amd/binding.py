@@ -24,6 +24,7 @@ PF_LBM_MAX_BODIES = 16
 PF_LBM_D3Q19 = 19
 PF_LBM_FP64 = 0
 PF_LBM_FP32 = 1
+PF_LBM_FP16_STORE = 2
 PF_LBM_KINETICS = 1
 PF_LBM_MOTION = 2
 PF_LBM_REPULSION = 4

@@ -73,7 +73,7 @@ struct BodyDev {
 struct StepState {
     int32_t box[2][6];            // lo x, lo y, lo z, hi x, hi y, hi z
     uint32_t err;                 // bit 0 non-finite body state, bit 1 advection CFL above 1
-    uint32_t events;              // nonzero when this step's reclassification changed any node
+    uint32_t n_events;            // nodes that changed side in this step's reclassification
     unsigned long long n_f2s, n_s2f, n_lost;
     float srad[PF_LBM_MAX_BODIES];  // largest distance of a solid node from its body's centre
 };
@@ -145,6 +145,49 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+// ---- population storage.  FP64 and FP32 store the populations themselves.  The FP16 form
+// stores each f_i(x) as the deviation f_i - w_i R(x) from its rest equilibrium, with the
+// reference density R(x) = -rho0 log(1 - psi(x)) taken from the node's pseudopotential of the
+// previous step (its density up to FP32 rounding), and does all arithmetic in FP32.  Writer and
+// reader evaluate R from the same stored psi with the same instructions, so they agree to the
+// bit; the deviations stay small (non-equilibrium and velocity parts), which keeps the FP16
+// rounding far below that of deviations from a fixed density.  Arith<S>::T is the arithmetic
+// type of storage S.
+using half_t = _Float16;
+template <typename S>
+struct Arith {
+    using T = S;
+};
+template <>
+struct Arith<half_t> {
+    using T = float;
+};
+template <typename S>
+using ArT = typename Arith<S>::T;
+
+// reference density of the FP16 form from a stored pseudopotential value (hardware log2)
+__device__ __forceinline__ float ref_density(float psi, float rho0) {
+    const float q = fmaxf(1.0f - psi, 1e-6f);
+    return -0.69314718f * rho0 * __log2f(q);
+}
+
+// stored value -> population, with wref = w_i R
+template <typename S>
+__device__ __forceinline__ ArT<S> pop_get(S v, ArT<S> wref) {
+    if constexpr (sizeof(S) == 2)
+        return wref + (float)v;
+    else
+        return v;
+}
+// population -> stored value
+template <typename S>
+__device__ __forceinline__ S pop_put(ArT<S> f, ArT<S> wref) {
+    if constexpr (sizeof(S) == 2)
+        return (S)(f - wref);
+    else
+        return f;
+}
+
 // ---- parameters passed by value to every kernel
 template <typename T>
 struct Prm {
@@ -155,6 +198,7 @@ struct Prm {
     T guo;           // 1 - 1 / (2 tau)
     T G;
     T inv_rho0;
+    T rho0;          // reference density of psi (the FP16 form's reference density uses it)
     T fext[3];
     int flags;       // PF_LBM_* step flags
     double threshold, mobility, eta, r_c, n_exp, e0, R_A;
@@ -172,28 +216,26 @@ __device__ __forceinline__ int fast_div(int k, int d, double inv_d) {
 
 // iteration over the cells of a box [lo, hi] (unwrapped coordinates, hi - lo + 1 <= n per axis)
 struct BoxIter {
-    int lo[3], ex, ey, vol, n[3];
+    int lo[3], ext[3], vol, n[3];
     double inv_ex, inv_ey;
     __device__ __forceinline__ BoxIter(const int32_t *b, int nx, int ny, int nz) {
-        lo[0] = b[0];
-        lo[1] = b[1];
-        lo[2] = b[2];
-        ex = b[3] - b[0] + 1;
-        ey = b[4] - b[1] + 1;
-        const int ez = b[5] - b[2] + 1;
-        vol = (ex > 0 && ey > 0 && ez > 0) ? ex * ey * ez : 0;
-        inv_ex = ex > 0 ? 1.0 / ex : 0.0;
-        inv_ey = ey > 0 ? 1.0 / ey : 0.0;
         n[0] = nx;
         n[1] = ny;
         n[2] = nz;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = b[d];
+            ext[d] = b[3 + d] - b[d] + 1;
+        }
+        vol = (ext[0] > 0 && ext[1] > 0 && ext[2] > 0) ? ext[0] * ext[1] * ext[2] : 0;
+        inv_ex = ext[0] > 0 ? 1.0 / ext[0] : 0.0;
+        inv_ey = ext[1] > 0 ? 1.0 / ext[1] : 0.0;
     }
     // cell k -> unwrapped (u) and wrapped (c) coordinates; the box spans at most one period
     __device__ __forceinline__ void cell(int k, int *u, int *c) const {
-        const int t = fast_div(k, ex, inv_ex);
-        const int zz = fast_div(t, ey, inv_ey);
-        u[0] = lo[0] + (k - t * ex);
-        u[1] = lo[1] + (t - zz * ey);
+        const int t = fast_div(k, ext[0], inv_ex);
+        const int zz = fast_div(t, ext[1], inv_ey);
+        u[0] = lo[0] + (k - t * ext[0]);
+        u[1] = lo[1] + (t - zz * ext[1]);
         u[2] = lo[2] + zz;
         for (int d = 0; d < 3; ++d) {
             int v = u[d];
@@ -201,6 +243,10 @@ struct BoxIter {
             v -= v >= n[d] ? n[d] : 0;
             c[d] = v;
         }
+    }
+    // does unwrapped coordinate v on axis d lie in the box (always, once the box spans the axis)
+    __device__ __forceinline__ bool inside(int d, int v) const {
+        return ext[d] >= n[d] || (v >= lo[d] && v < lo[d] + ext[d]);
     }
 };
 
@@ -227,7 +273,7 @@ __device__ __forceinline__ int wrap2(int i, int n) {
 //  * per body (wave 1 + b % 3): the solid radius (bounds the repulsion search) and the volume
 //    driving term h_a = (4 eta / pi^2) (V_ref - sum phi_a) / #{floor < phi_a < 1} (Sec. 3.3; 0
 //    without interface nodes), into the body table;
-// and clear the event flag for this step's reclassification.  Each lane sums its parts with four
+// and clear the event count for this step's reclassification.  Each lane sums its parts with four
 // independent accumulators, then a fixed xor-shuffle tree combines the lanes.
 __device__ __forceinline__ void publish_step_state(int wave, int parity, int nx, int ny, int nz, int nb, double eta,
                                                    StepState *st, BodyDev *bodies, const ClassifyPart *cpart,
@@ -260,7 +306,7 @@ __device__ __forceinline__ void publish_step_state(int wave, int parity, int nx,
                 st->box[parity][d] = empty ? 0 : l;
                 st->box[parity][3 + d] = empty ? -1 : h;
             }
-            st->events = 0u;
+            st->n_events = 0u;
         }
         return;
     }

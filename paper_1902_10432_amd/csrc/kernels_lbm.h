@@ -8,9 +8,12 @@ namespace pfl {
 
 // Pseudopotential psi = 1 - exp(-rho/rho0) of every fluid node; a solid node carries the value
 // of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.
-template <typename T>
-__global__ __launch_bounds__(256) void k_psi(Prm<T> p, const T *__restrict__ f, const cell_t *__restrict__ mask,
-                                             const BodyDev *__restrict__ bodies, T *__restrict__ psi) {
+// psi_ref: the pseudopotential of the previous step (reference density of the FP16 form).
+template <typename S>
+__global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, const S *__restrict__ f, const cell_t *__restrict__ mask,
+                                             const BodyDev *__restrict__ bodies, const ArT<S> *__restrict__ psi_ref,
+                                             ArT<S> *__restrict__ psi) {
+    using T = ArT<S>;
     const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed
     const cell_t m = mask[idx];
@@ -18,8 +21,10 @@ __global__ __launch_bounds__(256) void k_psi(Prm<T> p, const T *__restrict__ f, 
     if (m & C_SOLID) {
         out = (T)bodies[owner_of(m)].psi_s;
     } else {
+        // the weights sum to one: rho = R + sum of the stored deviations in the FP16 form
         T r = T(0);
-        sfor<19>([&](auto I) { r += f[(long long)I * p.Np + idx]; });
+        if constexpr (sizeof(S) == 2) r = ref_density(psi_ref[idx], p.rho0);
+        sfor<19>([&](auto I) { r += (T)f[(long long)I * p.Np + idx]; });
         out = -expm1(-r * p.inv_rho0);
     }
     psi[idx] = out;
@@ -120,11 +125,14 @@ __device__ __forceinline__ bool cell_of_block(int nx, int ny, int &x, int &y, in
 //   f*_i = (1 - 1/tau) f_i + w (even + odd),  f*_opp = (1 - 1/tau) f_opp + w (even - odd),
 //   even = rho/tau (1 - 3/2 v.v) - 3 g v.F + 9/2 rho/tau cu^2 + 9 g cu cF,  odd = 3 rho/tau cu + 3 g cF,
 // g = 1 - 1/(2 tau), which is the BGK relaxation to the second-order equilibrium plus the Guo term.
-template <typename T>
-__global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__restrict__ fin, T *__restrict__ fout,
-                                                        const T *__restrict__ psi, const cell_t *__restrict__ mask,
+template <typename S>
+__global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *__restrict__ fin, S *__restrict__ fout,
+                                                        const ArT<S> *__restrict__ psi,
+                                                        const ArT<S> *__restrict__ psi_prev,
+                                                        const cell_t *__restrict__ mask,
                                                         BodyDev *bodies, int parity, StepState *st,
                                                         const ClassifyPart *__restrict__ cpart, int cblk) {
+    using T = ArT<S>;
     if (cpart && (blockIdx.x | blockIdx.y | blockIdx.z) == 0)
         publish_step_state((int)threadIdx.y, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart, cblk);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
@@ -134,12 +142,20 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__res
     const cell_t w0 = mask[idx];
     if (w0 & C_SOLID) return;
     const uint32_t solid_dirs = w0 & C_NBMASK;
-    const uint32_t ib = idx * (uint32_t)sizeof(T);
+    const uint32_t ib = idx * (uint32_t)sizeof(T);      // psi (arithmetic type)
+    const uint32_t is = idx * (uint32_t)sizeof(S);      // populations (storage type)
     const NbrU nb(x, y, z, nx, ny, nz, (int)sizeof(T));
+    const NbrU ns(x, y, z, nx, ny, nz, (int)sizeof(S));
     const long long Np = p.Np;
+    constexpr bool H = sizeof(S) == 2;  // FP16 storage: deviations from w_i R
 
     T f[19];
-    sfor<19>([&](auto I) { f[I] = ldb(fin + (long long)I * Np, ib); });
+    {
+        const T rin = H ? ref_density(psi_prev[idx], p.rho0) : T(0);  // reference of the inputs
+        sfor<19>([&](auto I) {
+            f[I] = pop_get<S>(ldb(fin + (long long)I * Np, is), Dir<decltype(I)::value>::template w<T>() * rin);
+        });
+    }
     // moments from pair sums and differences
     T rho = f[0], jx = T(0), jy = T(0), jz = T(0);
     sfor<9>([&](auto K) {
@@ -156,9 +172,15 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__res
 
     // pseudopotential force from pair differences of the neighbours' psi
     T s1x = T(0), s1y = T(0), s1z = T(0), s2x = T(0), s2y = T(0), s2z = T(0);
+    T rdst[19];  // FP16 form: reference density of each push destination
     sfor<9>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;
-        const T dp = ldb(psi, nb.template at<i>(ib)) - ldb(psi, nb.template at<i + 1>(ib));
+        const T pa = ldb(psi, nb.template at<i>(ib)), pb = ldb(psi, nb.template at<i + 1>(ib));
+        if constexpr (H) {
+            rdst[i] = ref_density(pa, p.rho0);
+            rdst[i + 1] = ref_density(pb, p.rho0);
+        }
+        const T dp = pa - pb;
         if constexpr (Dir<i>::c2 == 1) {
             if constexpr (Dir<i>::x != 0) s1x += T(Dir<i>::x) * dp;
             if constexpr (Dir<i>::y != 0) s1y += T(Dir<i>::y) * dp;
@@ -169,7 +191,9 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__res
             if constexpr (Dir<i>::z != 0) s2z += T(Dir<i>::z) * dp;
         }
     });
-    const T gp = -p.G * ldb(psi, ib);
+    const T psi0 = ldb(psi, ib);
+    const T gp = -p.G * psi0;
+    const T rown = H ? ref_density(psi0, p.rho0) : T(0);  // reference of this node's own slots
     const T w1 = T(1.0 / 18.0), w2 = T(1.0 / 36.0);
     const T Fx = gp * (w1 * s1x + w2 * s2x) + p.fext[0];
     const T Fy = gp * (w1 * s1y + w2 * s2y) + p.fext[1];
@@ -202,9 +226,10 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__res
     if (!solid_dirs) {
         sfor<19>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            if constexpr (i > 0) stb(fout + (long long)i * Np, nb.template at<i>(ib), f[i]);
+            if constexpr (i > 0)
+                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i>::template w<T>() * rdst[i]));
         });
-        stb(fout, ib, f[0]);
+        stb(fout, is, pop_put<S>(f[0], Dir<0>::template w<T>() * rown));
         return;
     }
     const NbrU ne(x, y, z, nx, ny, nz, 1);
@@ -213,7 +238,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__res
         constexpr int i = decltype(I)::value;
         if constexpr (i > 0) {
             if (!(solid_dirs & (1u << i))) {
-                stb(fout + (long long)i * Np, nb.template at<i>(ib), f[i]);
+                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i>::template w<T>() * rdst[i]));
             } else {
                 // reflected into direction opp(i) with g = -2 rho w_i (c_i . u_w) / c_s^2, u_w at
                 // the link midpoint x + c_i / 2
@@ -222,12 +247,12 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<T> p, const T *__res
                 wall_velocity(p, Bd, x + 0.5 * Dir<i>::x, y + 0.5 * Dir<i>::y, z + 0.5 * Dir<i>::z, uwx, uwy, uwz);
                 const double cuw = Dir<i>::x * uwx + Dir<i>::y * uwy + Dir<i>::z * uwz;
                 const T gw = T(-6.0 * Dir<i>::template w<double>() * cuw) * rho;
-                stb(fout + (long long)Dir<i>::opp * Np, ib, f[i] + gw);
+                stb(fout + (long long)Dir<i>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i>::template w<T>() * rown));
                 drho += gw;
             }
         }
     });
-    stb(fout, ib, f[0] - drho);
+    stb(fout, is, pop_put<S>(f[0] - drho, Dir<0>::template w<T>() * rown));
 }
 
 // Per-body force and torque sums of the step, one box node per thread (Sec. 3.1.1, 3.1.2, 3.2.2):
@@ -249,11 +274,14 @@ constexpr int force_waves() {
     return sizeof(T) == 4 ? 12 : 8;
 }
 
-template <typename T>
-__global__ __launch_bounds__(64 * force_waves<T>()) void k_body_forces(Prm<T> p, int parity, const StepState *st,
-                                                     const T *__restrict__ fin, const T *__restrict__ fpost,
-                                                     const T *__restrict__ psi, const cell_t *__restrict__ mask,
+template <typename S>
+__global__ __launch_bounds__(64 * force_waves<ArT<S>>()) void k_body_forces(Prm<ArT<S>> p, int parity,
+                                                     const StepState *st, const S *__restrict__ fin,
+                                                     const S *__restrict__ fpost, const ArT<S> *__restrict__ psi,
+                                                     const ArT<S> *__restrict__ psi_prev,
+                                                     const cell_t *__restrict__ mask,
                                                      const BodyDev *__restrict__ bodies, double *part) {
+    using T = ArT<S>;
     constexpr int W = force_waves<T>(), NT = 64 * W;
     __shared__ double acc[W][PF_LBM_MAX_BODIES][6];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -297,8 +325,11 @@ __global__ __launch_bounds__(64 * force_waves<T>()) void k_body_forces(Prm<T> p,
                     // one round of independent gathers (byte offsets from uniform bases)
                     const NbrU ne(x, y, z, nx, ny, nz, 1);
                     const uint32_t ib = (uint32_t)idx * (uint32_t)sizeof(T);
-                    sfor<19>([&](auto I) { rho += ldb(fin + (long long)I * Np, ib); });
+                    const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
+                    rho = sizeof(S) == 2 ? ref_density(psi_prev[idx], p.rho0) : T(0);
+                    sfor<19>([&](auto I) { rho += (T)ldb(fin + (long long)I * Np, is); });
                     ps0 = ldb(psi, ib);
+                    const T rown = sizeof(S) == 2 ? ref_density(ps0, p.rho0) : T(0);
                     const T gp = p.G * ps0;
                     sfor<19>([&](auto I) {
                         constexpr int i = decltype(I)::value;
@@ -309,7 +340,8 @@ __global__ __launch_bounds__(64 * force_waves<T>()) void k_body_forces(Prm<T> p,
                                 const uint32_t o = (uint32_t)owner_of(ldb(mask, n * 4u));
                                 own[i >> 3] |= o << (4 * (i & 7));
                                 touched |= 1u << o;
-                                a[i] = T(2) * ldb(fpost + (long long)Dir<i>::opp * Np, ib) +
+                                a[i] = T(2) * pop_get<S>(ldb(fpost + (long long)Dir<i>::opp * Np, is),
+                                                         Dir<i>::template w<T>() * rown) +
                                        gp * Dir<i>::template w<T>() * ldb(psi, n * (uint32_t)sizeof(T));
                             }
                         }

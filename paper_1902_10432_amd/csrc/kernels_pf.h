@@ -114,22 +114,30 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
     const int L = n[AX];
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
     uint32_t cfl = 0;
-    for (int k = blockIdx.x * 256 + tid; k < it.vol; k += gridDim.x * 256) {
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    for (int k = bid * 256 + tid; k < it.vol; k += gridDim.x * 256) {
         int u[3], c[3];
         it.cell(k, u, c);
         const int idx = c[0] + p.nx * (c[1] + p.ny * c[2]);
         const int i = c[AX];
-        // flat indices of the five cells i-2..i+2 along the axis (periodic)
+        // flat indices of the five cells i-2..i+2 along the axis (periodic); cells outside the
+        // box hold no phase (the support stays 3 cells inside it through the step) and are not
+        // read, so the intermediate buffers need no clearing outside the box
         int off[5];
+        bool in[5];
 #pragma unroll
-        for (int s = -2; s <= 2; ++s) off[s + 2] = idx + (wrap2(i + s, L) - i) * step;
+        for (int s = -2; s <= 2; ++s) {
+            off[s + 2] = idx + (wrap2(i + s, L) - i) * step;
+            in[s + 2] = it.inside(AX, u[AX] + s);
+        }
         for (int a = 0; a < nbod; ++a) {
             // velocity component along AX at this sweep line
             const double r1 = mimg_r((double)c[A1] - lb[a][A1], n[A1], p.inv_n[A1]);
             const double r2 = mimg_r((double)c[A2] - lb[a][A2], n[A2], p.inv_n[A2]);
             const double uu = lb[a][3 + AX] + (lb[a][6 + A1] * r2 - lb[a][6 + A2] * r1);
             const double *s0 = src + (long long)a * Np;
-            const double vm2 = s0[off[0]], vm1 = s0[off[1]], v0 = s0[off[2]], v1 = s0[off[3]], v2 = s0[off[4]];
+            const double vm2 = in[0] ? s0[off[0]] : 0.0, vm1 = in[1] ? s0[off[1]] : 0.0, v0 = s0[off[2]],
+                         v1 = in[3] ? s0[off[3]] : 0.0, v2 = in[4] ? s0[off[4]] : 0.0;
             const double Fp = mc_flux(uu, vm1, v0, v1, v2);
             const double Fm = mc_flux(uu, vm2, vm1, v0, v1);
             dst[(long long)a * Np + idx] = v0 - (Fp - Fm);
@@ -139,130 +147,281 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
     if (cfl) atomicOr(&st->err, 2u);  // rare: only when the input breaks the CFL bound
 }
 
-// Multi-phase-field kinetics (Sec. 3.3), explicit Euler, for nodes where at least two phases are
-// active (above the floor at the node or a face neighbour; phase 0 = fluid = 1 - sum of solids):
-//   dphi_a/dt = sum_{b active, b != a} (M/N) ( sigma_ab (I_a - I_b)
-//               + sum_{g active, g != a, b} (sigma_bg - sigma_ag) I_g + pi^2/(4 eta) (h_a - h_b) ),
-//   I = lap(phi) + (pi^2/eta^2) phi with the 7-point Laplacian, h_fluid = 0 and h_a the volume
-//   driving term of the body table (set at the start of the step from the phase fields before
-//   advection, which leaves the volumes unchanged).
-// Then each solid phase is clipped to [0, 1] (values below the floor to 0) and the solids are
-// rescaled if their sum exceeds 1.  Without kinetics the kernel copies.  src -> dst over the box.
+// Classification of one node from its final phase values (Sec. 3.2.2): solid iff the fluid
+// fraction 1 - sum phi is below the threshold, owner = argmax phi (lowest index on ties).
+template <int NBMAX>
+__device__ __forceinline__ void classify_node(const double *phi_a, int nbod, double threshold, bool &solid, int &arg,
+                                              double &sum) {
+    double best = -1.0;
+    sum = 0.0;
+    arg = 0;
+#pragma unroll
+    for (int a = 0; a < NBMAX; ++a) {
+        if (a >= nbod) break;
+        const double v = phi_a[a];
+        sum += v;
+        if (v > best) {
+            best = v;
+            arg = a;
+        }
+    }
+    solid = nbod > 0 && (1.0 - sum) < threshold;
+}
+
+// Phase-field update of the step after the advection sweeps, one box node per thread:
+//  * multi-phase-field kinetics (Sec. 3.3), explicit Euler, for nodes where at least two phases
+//    are active (above the floor at the node or a face neighbour; phase 0 = fluid = 1 - sum of
+//    solids):
+//      dphi_a/dt = sum_{b active, b != a} (M/N) ( sigma_ab (I_a - I_b)
+//                  + sum_{g active, g != a, b} (sigma_bg - sigma_ag) I_g + pi^2/(4 eta) (h_a - h_b) ),
+//    I = lap(phi) + (pi^2/eta^2) phi with the 7-point Laplacian, h_fluid = 0 and h_a the volume
+//    driving term of the body table (set at the start of the step from the phase fields before
+//    advection, which leaves the volumes unchanged); then each solid phase is clipped to [0, 1]
+//    (values below the floor to 0) and the solids are rescaled if their sum exceeds 1; without
+//    kinetics the phase values pass unchanged;
+//  * reclassification of the node (Sec. 3.2.2) and, for a node that changed side (rare), an
+//    entry in the step's event list: cell index, bit 31 set when it became solid;
+//  * per-block results for the next step (publish_step_state): support bounds in unwrapped
+//    coordinates, per-body solid radius, sum of phi and count of interface nodes.
+// Face neighbours outside the box hold no phase and are not read.
 template <typename PT, int NBMAX>
-__global__ __launch_bounds__(256) void k_kinetics(Prm<PT> p, int parity, const StepState *st,
-                                                  const BodyDev *__restrict__ bodies, const double *__restrict__ sigma,
-                                                  const double *__restrict__ src, double *__restrict__ dst) {
+__global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, StepState *st,
+                                                      const BodyDev *__restrict__ bodies,
+                                                      const double *__restrict__ sigma, const double *__restrict__ src,
+                                                      double *__restrict__ dst, cell_t *__restrict__ mask, ClassifyPart *__restrict__ cpart,
+                                                      uint32_t *__restrict__ evlist, uint32_t evcap) {
     using T = double;  // phase fields are FP64 in every precision form
     constexpr int NP = NBMAX + 1;
     __shared__ double sg[NP * NP];
     __shared__ double hh[NP];
+    __shared__ int32_t sb[4][6];
+    __shared__ uint32_t sc[4][2];
+    __shared__ float sr[4][NBMAX];
+    __shared__ double sv[4][NBMAX];
+    __shared__ uint32_t si[4][NBMAX];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nbod = p.nb, np1 = nbod + 1;
-    for (int k = threadIdx.x; k < np1 * np1; k += 256) sg[(k / np1) * NP + (k % np1)] = sigma[k];
-    if (threadIdx.x < np1) hh[threadIdx.x] = threadIdx.x == 0 ? 0.0 : bodies[threadIdx.x - 1].h;
+    for (int k = tid; k < np1 * np1; k += 256) sg[(k / np1) * NP + (k % np1)] = sigma[k];
+    if (tid < np1) hh[tid] = tid == 0 ? 0.0 : bodies[tid - 1].h;
     __syncthreads();
     const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
-    const bool kin = (p.flags & 1) != 0;
+    const bool kin = (p.flags & PF_LBM_KINETICS) != 0;
     const T PI = T(3.14159265358979323846);
     const T mu = PI * PI / (T)(p.eta * p.eta);
     const T vterm = PI * PI / (T)(4.0 * p.eta);
     const T M = (T)p.mobility;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < it.vol; k += gridDim.x * 256) {
-        int u[3], c[3];
-        it.cell(k, u, c);
-        const int x = c[0], y = c[1], z = c[2];
-        const int idx = x + nx * (y + ny * z);
-        T v0[NP];
+    // per-thread partial results, combined per block at the end
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    uint32_t f2s = 0, s2f = 0;
+    float rad[NBMAX];
+    double vol[NBMAX];
+    uint32_t icnt[NBMAX];
 #pragma unroll
-        for (int a = 0; a < NBMAX; ++a) v0[a + 1] = a < nbod ? src[(long long)a * Np + idx] : T(0);
-        if (!kin) {
+    for (int a = 0; a < NBMAX; ++a) {
+        rad[a] = 0.0f;
+        vol[a] = 0.0;
+        icnt[a] = 0u;
+    }
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    for (int base = bid * 256; base < it.vol; base += gridDim.x * 256) {
+        const int k = base + tid;
+        uint32_t event = 0;  // list entry + 1, 0 = none
+        if (k < it.vol) {
+            int u[3], c[3];
+            it.cell(k, u, c);
+            const int x = c[0], y = c[1], z = c[2];
+            const int idx = x + nx * (y + ny * z);
+            T v0[NP];
+#pragma unroll
+            for (int a = 0; a < NBMAX; ++a) v0[a + 1] = a < nbod ? src[(long long)a * Np + idx] : T(0);
+            T out[NP];
+#pragma unroll
+            for (int a = 1; a < NP; ++a) out[a] = v0[a];
+            if (kin) {
+                const Nbr nb(x, y, z, nx, ny, nz);
+                const int offs[6] = {nb.xp, nb.xm, nb.yp, nb.ym, nb.zp, nb.zm};
+                const bool ins[6] = {it.inside(0, u[0] + 1), it.inside(0, u[0] - 1), it.inside(1, u[1] + 1),
+                                     it.inside(1, u[1] - 1), it.inside(2, u[2] + 1), it.inside(2, u[2] - 1)};
+                T sum0 = T(0);
+#pragma unroll
+                for (int a = 0; a < NBMAX; ++a) sum0 += v0[a + 1];
+                v0[0] = T(1) - sum0;
+                T lap[NP];
+                bool on[NP];
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    lap[q] = T(-6) * v0[q];
+                    on[q] = v0[q] > T(PHI_FLOOR);
+                }
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    T s = T(0);
+#pragma unroll
+                    for (int a = 0; a < NBMAX; ++a) {
+                        const T v = (a < nbod && ins[e]) ? src[(long long)a * Np + idx + offs[e]] : T(0);
+                        s += v;
+                        lap[a + 1] += v;
+                        on[a + 1] = on[a + 1] || v > T(PHI_FLOOR);
+                    }
+                    const T vf = T(1) - s;
+                    lap[0] += vf;
+                    on[0] = on[0] || vf > T(PHI_FLOOR);
+                }
+                int na = 0;
+                T I[NP];
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    if (q > nbod) on[q] = false;
+                    I[q] = lap[q] + mu * v0[q];
+                    na += on[q] ? 1 : 0;
+                }
+                T tot = T(0);
+#pragma unroll
+                for (int a = 1; a < NP; ++a) {
+                    T nv = v0[a];
+                    if (na >= 2 && on[a]) {
+                        T rate = T(0);
+#pragma unroll
+                        for (int b = 0; b < NP; ++b) {
+                            if (b == a || !on[b]) continue;
+                            T t = (T)sg[a * NP + b] * (I[a] - I[b]);
+#pragma unroll
+                            for (int g = 0; g < NP; ++g) {
+                                if (g == a || g == b || !on[g]) continue;
+                                t += ((T)sg[b * NP + g] - (T)sg[a * NP + g]) * I[g];
+                            }
+                            t += vterm * (T)(hh[a] - hh[b]);
+                            rate += (M / T(na)) * t;
+                        }
+                        nv = v0[a] + rate;
+                    }
+                    nv = nv < T(PHI_FLOOR) ? T(0) : (nv > T(1) ? T(1) : nv);
+                    out[a] = nv;
+                    tot += nv;
+                }
+                if (tot > T(1)) {
+#pragma unroll
+                    for (int a = 1; a < NP; ++a) out[a] /= tot;
+                }
+            }
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a)
-                if (a < nbod) dst[(long long)a * Np + idx] = v0[a + 1];
-            continue;
-        }
-        const Nbr nb(x, y, z, nx, ny, nz);
-        const int offs[6] = {nb.xp, nb.xm, nb.yp, nb.ym, nb.zp, nb.zm};
-        T sum0 = T(0);
-#pragma unroll
-        for (int a = 0; a < NBMAX; ++a) sum0 += v0[a + 1];
-        v0[0] = T(1) - sum0;
-        T lap[NP];
-        bool on[NP];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            lap[q] = T(-6) * v0[q];
-            on[q] = v0[q] > T(PHI_FLOOR);
-        }
-#pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            T s = T(0);
+                if (a < nbod) dst[(long long)a * Np + idx] = out[a + 1];
+            // reclassification
+            bool solid;
+            int arg;
+            double sum;
+            classify_node<NBMAX>(out + 1, nbod, p.threshold, solid, arg, sum);
+            const cell_t old = mask[idx];
+            cell_t m = (old & C_NBMASK) | (solid ? solid_word(arg) : 0u);
+            if (solid && !(old & C_SOLID)) {
+                m |= C_F2S;
+                ++f2s;
+                event = ((uint32_t)idx | 0x80000000u) + 1u;
+            }
+            if (!solid && (old & C_SOLID)) {
+                m |= C_S2F;
+                ++s2f;
+                event = (uint32_t)idx + 1u;
+            }
+            if (m != old) mask[idx] = m;
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a) {
-                const T v = a < nbod ? src[(long long)a * Np + idx + offs[e]] : T(0);
-                s += v;
-                lap[a + 1] += v;
-                on[a + 1] = on[a + 1] || v > T(PHI_FLOOR);
+                if (a >= nbod) break;
+                vol[a] += out[a + 1];
+                icnt[a] += (out[a + 1] > PHI_FLOOR && out[a + 1] < 1.0) ? 1u : 0u;
             }
-            const T vf = T(1) - s;
-            lap[0] += vf;
-            on[0] = on[0] || vf > T(PHI_FLOOR);
-        }
-        int na = 0;
-        T I[NP];
+            if (solid) {
+                // distance of this solid node from its body's centre (bounds the repulsion search)
+                const BodyDev &B = bodies[arg];
+                const double rx = mimg_r(x - B.X[0], nx, p.inv_n[0]), ry = mimg_r(y - B.X[1], ny, p.inv_n[1]),
+                             rz = mimg_r(z - B.X[2], nz, p.inv_n[2]);
+                const float r = (float)sqrt(rx * rx + ry * ry + rz * rz) + 1e-3f;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            if (q > nbod) on[q] = false;
-            I[q] = lap[q] + mu * v0[q];
-            na += on[q] ? 1 : 0;
-        }
-        T out[NP];
-        T tot = T(0);
-#pragma unroll
-        for (int a = 1; a < NP; ++a) {
-            T nv = v0[a];
-            if (na >= 2 && on[a]) {
-                T rate = T(0);
-#pragma unroll
-                for (int b = 0; b < NP; ++b) {
-                    if (b == a || !on[b]) continue;
-                    T t = (T)sg[a * NP + b] * (I[a] - I[b]);
-#pragma unroll
-                    for (int g = 0; g < NP; ++g) {
-                        if (g == a || g == b || !on[g]) continue;
-                        t += ((T)sg[b * NP + g] - (T)sg[a * NP + g]) * I[g];
-                    }
-                    t += vterm * (T)(hh[a] - hh[b]);
-                    rate += (M / T(na)) * t;
+                for (int a = 0; a < NBMAX; ++a)
+                    if (a == arg) rad[a] = fmaxf(rad[a], r);
+            }
+            if (sum > 0.0) {
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = min(lo[d], u[d]);
+                    hi[d] = max(hi[d], u[d]);
                 }
-                nv = v0[a] + rate;
             }
-            nv = nv < T(PHI_FLOOR) ? T(0) : (nv > T(1) ? T(1) : nv);
-            out[a] = nv;
-            tot += nv;
         }
-        if (tot > T(1)) {
-#pragma unroll
-            for (int a = 1; a < NP; ++a) out[a] /= tot;
+        // event list: one atomic per wave that saw a node change side (rare)
+        const unsigned long long bal = __ballot(event != 0);
+        if (bal) {
+            uint32_t slot0 = 0;
+            if (lane == 0) slot0 = atomicAdd(&st->n_events, (uint32_t)__popcll(bal));
+            slot0 = __shfl(slot0, 0, 64);
+            if (event) {
+                const uint32_t slot = slot0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                if (slot < evcap) evlist[slot] = event - 1u;
+            }
         }
+    }
+    // block results
+    for (int d = 0; d < 3; ++d) {
+        const int l = wave_min(lo[d]), h = wave_max(hi[d]);
+        if (lane == 0) {
+            sb[wave][d] = l;
+            sb[wave][3 + d] = h;
+        }
+    }
+    const uint32_t a2 = (uint32_t)wave_sum((int)f2s), b2 = (uint32_t)wave_sum((int)s2f);
+    if (lane == 0) {
+        sc[wave][0] = a2;
+        sc[wave][1] = b2;
+    }
 #pragma unroll
-        for (int a = 0; a < NBMAX; ++a)
-            if (a < nbod) dst[(long long)a * Np + idx] = out[a + 1];
+    for (int a = 0; a < NBMAX; ++a) {
+        if (a >= nbod) break;
+        float r = rad[a];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
+        const double v = wave_sum(vol[a]);
+        const int ic = wave_sum((int)icnt[a]);
+        if (lane == 0) {
+            sr[wave][a] = r;
+            sv[wave][a] = v;
+            si[wave][a] = (uint32_t)ic;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        ClassifyPart cp;
+        for (int d = 0; d < 3; ++d) {
+            cp.lo[d] = min(min(sb[0][d], sb[1][d]), min(sb[2][d], sb[3][d]));
+            cp.hi[d] = max(max(sb[0][3 + d], sb[1][3 + d]), max(sb[2][3 + d], sb[3][3 + d]));
+        }
+        cp.f2s = sc[0][0] + sc[1][0] + sc[2][0] + sc[3][0];
+        cp.s2f = sc[0][1] + sc[1][1] + sc[2][1] + sc[3][1];
+        for (int b = 0; b < PF_LBM_MAX_BODIES; ++b) {
+            const bool on = b < nbod;
+            cp.srad[b] = on ? fmaxf(fmaxf(sr[0][b], sr[1][b]), fmaxf(sr[2][b], sr[3][b])) : 0.0f;
+            cp.vol[b] = on ? ((sv[0][b] + sv[1][b]) + sv[2][b]) + sv[3][b] : 0.0;
+            cp.icnt[b] = on ? si[0][b] + si[1][b] + si[2][b] + si[3][b] : 0u;
+        }
+        cpart[blockIdx.x] = cp;
+        if (cp.f2s + cp.s2f) {  // rare: nodes of this block changed side
+            atomicAdd(&st->n_f2s, (unsigned long long)cp.f2s);
+            atomicAdd(&st->n_s2f, (unsigned long long)cp.s2f);
+        }
     }
 }
 
-// Reclassification (Sec. 3.2.2): solid iff the fluid fraction 1 - sum phi is below the
-// threshold, owner = argmax phi (lowest index on ties).  Marks the nodes that changed side (and,
-// rarely, raises the step's event flag and adds to the conversion counts) and copies the final
-// phase fields into the second buffer.  Each block writes to cpart[block] its support bounds
-// (unwrapped coordinates), per-body solid radius, per-body sum of phi and count of interface
-// nodes floor < phi < 1, which the next step's first kernel combines (publish_step_state).
+// Classification of the initial phase fields (Sec. 3.2.2): solid iff the fluid fraction
+// 1 - sum phi is below the threshold, owner = argmax phi (lowest index on ties).  Each block
+// writes to cpart[block] its support bounds (unwrapped coordinates), per-body solid radius, sum
+// of phi and count of interface nodes floor < phi < 1, which the first step publishes.  (During
+// the run the phase-update kernel classifies.)
 template <typename PT>
-__global__ __launch_bounds__(256) void k_classify(Prm<PT> p, int parity, StepState *st,
-                                                  const BodyDev *__restrict__ bodies, const double *__restrict__ phi,
-                                                  double *__restrict__ phi_copy, cell_t *__restrict__ mask, int init,
-                                                  ClassifyPart *cpart) {
+__global__ __launch_bounds__(256) void k_classify_init(Prm<PT> p, int parity, const StepState *st,
+                                                       const BodyDev *__restrict__ bodies,
+                                                       const double *__restrict__ phi, cell_t *__restrict__ mask,
+                                                       ClassifyPart *cpart) {
     using T = double;
     __shared__ int32_t sb[4][6];
     __shared__ uint32_t sc[4][2];
@@ -296,7 +455,6 @@ __global__ __launch_bounds__(256) void k_classify(Prm<PT> p, int parity, StepSta
         int arg = 0;
         for (int a = 0; a < nbod; ++a) {
             const T v = valid ? phi[(long long)a * Np + idx] : T(0);
-            if (valid && phi_copy) phi_copy[(long long)a * Np + idx] = v;
             sum += v;
             if (v > best) {
                 best = v;
@@ -311,19 +469,7 @@ __global__ __launch_bounds__(256) void k_classify(Prm<PT> p, int parity, StepSta
         }
         if (!valid) continue;
         const bool solid = nbod > 0 && (T(1) - sum) < (T)p.threshold;
-        const cell_t old = mask[idx];
-        cell_t m = (old & C_NBMASK) | (solid ? solid_word(arg) : 0u);
-        if (!init) {
-            if (solid && !(old & C_SOLID)) {
-                m |= C_F2S;
-                ++f2s;
-            }
-            if (!solid && (old & C_SOLID)) {
-                m |= C_S2F;
-                ++s2f;
-            }
-        }
-        if (m != old) mask[idx] = m;
+        mask[idx] = solid ? solid_word(arg) : 0u;
         if (solid) {
             // distance of this solid node from its body's centre (bounds the repulsion search)
             const BodyDev &B = bodies[arg];
@@ -374,11 +520,6 @@ __global__ __launch_bounds__(256) void k_classify(Prm<PT> p, int parity, StepSta
             cp.icnt[b] = on ? si[0][b] + si[1][b] + si[2][b] + si[3][b] : 0u;
         }
         cpart[blockIdx.x] = cp;
-        if (cp.f2s + cp.s2f) {  // rare: nodes of this block changed side
-            atomicOr(&st->events, 1u);
-            atomicAdd(&st->n_f2s, (unsigned long long)cp.f2s);
-            atomicAdd(&st->n_s2f, (unsigned long long)cp.s2f);
-        }
     }
 }
 
@@ -422,102 +563,196 @@ __device__ __forceinline__ int conversion_radius(const cell_t *mask, int x, int 
     return 0;
 }
 
-// Node conversion, receiving side (Sec. 3.2.2): every fluid node gathers, from each neighbour
-// that just became solid and whose neighbourhood N_F contains it, f_eq(rho_n, u_n) / |N_F| with
-// rho_n, u_n = j_n / rho_n of the converted node's populations.  A node that just became fluid
-// starts from empty populations.  Sources are only read here and emptied by k_post.  When no
-// node changed side this step (the usual case) the kernel returns at once.
-template <typename T>
-__global__ __launch_bounds__(256) void k_convert_gather(Prm<T> p, int parity, const StepState *st,
-                                                        const cell_t *__restrict__ mask, T *f) {
-    if (!st->events) return;
-    const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
+// Node conversion at one fluid node r (Sec. 3.2.2): the node gathers, from each neighbour that
+// just became solid and whose neighbourhood N_F contains it, f_eq(rho_n, u_n) / |N_F| with
+// rho_n, u_n = j_n / rho_n of the converted node's populations; a node that just became fluid
+// starts from empty populations.  Sources are only read here (k_post empties them).
+// psi: the pseudopotential of this step (reference density of the FP16 form)
+template <typename S>
+__device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__ mask, S *f,
+                                const ArT<S> *__restrict__ psi, int x, int y, int z, int idx, cell_t m) {
+    using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < it.vol; k += gridDim.x * 256) {
-        int u[3], c[3];
-        it.cell(k, u, c);
-        const int x = c[0], y = c[1], z = c[2];
-        const int idx = x + nx * (y + ny * z);
-        const cell_t m = mask[idx];
+    constexpr bool H = sizeof(S) == 2;
+    const T rr = H ? ref_density(psi[idx], p.rho0) : T(0);
+    T acc[19];
+    sfor<19>([&](auto I) {
+        acc[I] = (m & C_S2F) ? T(0)
+                             : pop_get<S>(f[(long long)I * Np + idx], Dir<decltype(I)::value>::template w<T>() * rr);
+    });
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 == 0) continue;
+                const int sx = wrapi(x + dx, nx), sy = wrapi(y + dy, ny), sz = wrapi(z + dz, nz);
+                const int n = sx + nx * (sy + ny * sz);
+                if (!(mask[n] & C_F2S)) continue;
+                double r2;
+                const int cnt = conversion_radius(mask, sx, sy, sz, nx, ny, nz, p.R_A, r2);
+                if (cnt == 0 || d2 > r2 + 1e-9) continue;
+                T fs[19];
+                const T rn = H ? ref_density(psi[n], p.rho0) : T(0);
+                sfor<19>([&](auto I) {
+                    fs[I] = pop_get<S>(f[(long long)I * Np + n], Dir<decltype(I)::value>::template w<T>() * rn);
+                });
+                T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
+                sfor<19>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    rho += fs[i];
+                    jx += T(Dir<i>::x) * fs[i];
+                    jy += T(Dir<i>::y) * fs[i];
+                    jz += T(Dir<i>::z) * fs[i];
+                });
+                T vx = T(0), vy = T(0), vz = T(0);
+                if (rho > T(0)) {
+                    vx = jx / rho;
+                    vy = jy / rho;
+                    vz = jz / rho;
+                }
+                const T inv = T(1) / T(cnt);
+                sfor<19>([&](auto I) { acc[I] += feq_dir<T, decltype(I)::value>(rho, vx, vy, vz) * inv; });
+            }
+    sfor<19>([&](auto I) {
+        f[(long long)I * Np + idx] = pop_put<S>(acc[I], Dir<decltype(I)::value>::template w<T>() * rr);
+    });
+}
+
+// does any of the 26 neighbours of (x, y, z) with a cell index below `below` carry the "became
+// solid" mark (below = 0xFFFFFFFF: any neighbour)
+__device__ __forceinline__ bool f2s_neighbour(const cell_t *mask, int x, int y, int z, int nx, int ny, int nz,
+                                              uint32_t below) {
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                const uint32_t n = (uint32_t)(wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz)));
+                if ((mask[n] & C_F2S) && n < below) return true;
+            }
+    return false;
+}
+
+// Node conversion, receiving side, after the reclassification of the step.  Usual case: no node
+// changed side and the kernel returns at once.  Otherwise the event list drives it: work item
+// (event e, neighbour d) handles the fluid node r = e + d when e is the converted node of lowest
+// index among r's neighbours (so each receiver is handled once, in a fixed order of its sources),
+// and a node that became fluid with no converted neighbour is emptied.  When the list overflowed,
+// the whole box is scanned instead.
+template <typename S>
+__global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parity, const StepState *st,
+                                                        const cell_t *__restrict__ mask, S *f,
+                                                        const ArT<S> *__restrict__ psi,
+                                                        const uint32_t *__restrict__ evlist, uint32_t evcap) {
+    using T = ArT<S>;
+    const uint32_t nev = st->n_events;
+    if (!nev) return;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const long long Np = p.Np;
+    const int gtid = blockIdx.x * 256 + threadIdx.x, gstride = gridDim.x * 256;
+    if (nev > evcap) {
+        const BoxIter it(st->box[parity], nx, ny, nz);
+        for (int k = gtid; k < it.vol; k += gstride) {
+            int u[3], c[3];
+            it.cell(k, u, c);
+            const int idx = c[0] + nx * (c[1] + ny * c[2]);
+            const cell_t m = mask[idx];
+            if (m & C_SOLID) continue;
+            if (!(m & C_S2F) && !f2s_neighbour(mask, c[0], c[1], c[2], nx, ny, nz, 0xFFFFFFFFu)) continue;
+            gather_receiver(p, mask, f, psi, c[0], c[1], c[2], idx, m);
+        }
+        return;
+    }
+    for (int j = gtid; j < (int)nev * 27; j += gstride) {
+        const uint32_t ent = evlist[j / 27];
+        const int d = j % 27;  // 13 = the event node itself
+        const uint32_t e = ent & 0x7FFFFFFFu;
+        const int ex = (int)(e % (uint32_t)nx), ey = (int)((e / (uint32_t)nx) % (uint32_t)ny), ez = (int)(e / ((uint32_t)nx * ny));
+        if (d == 13) {
+            // a node that became fluid with no converted neighbour starts empty
+            const cell_t m = mask[e];
+            if ((m & C_S2F) && !f2s_neighbour(mask, ex, ey, ez, nx, ny, nz, 0xFFFFFFFFu)) {
+                const T re = sizeof(S) == 2 ? ref_density(psi[e], p.rho0) : T(0);
+                sfor<19>([&](auto I) {
+                    f[(long long)I * Np + e] = pop_put<S>(T(0), Dir<decltype(I)::value>::template w<T>() * re);
+                });
+            }
+            continue;
+        }
+        if (!(ent & 0x80000000u)) continue;  // only nodes that became solid hand on mass
+        const int rx = wrapi(ex + d % 3 - 1, nx), ry = wrapi(ey + (d / 3) % 3 - 1, ny), rz = wrapi(ez + d / 9 - 1, nz);
+        const int r = rx + nx * (ry + ny * rz);
+        const cell_t m = mask[r];
         if (m & C_SOLID) continue;
-        bool any = (m & C_S2F) != 0;
-        for (int dz = -1; dz <= 1 && !any; ++dz)
-            for (int dy = -1; dy <= 1 && !any; ++dy)
-                for (int dx = -1; dx <= 1 && !any; ++dx) {
-                    if (!dx && !dy && !dz) continue;
-                    const int n = wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz));
-                    if (mask[n] & C_F2S) any = true;
-                }
-        if (!any) continue;
-        T acc[19];
-        sfor<19>([&](auto I) { acc[I] = (m & C_S2F) ? T(0) : f[(long long)I * Np + idx]; });
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 == 0) continue;
-                    const int sx = wrapi(x + dx, nx), sy = wrapi(y + dy, ny), sz = wrapi(z + dz, nz);
-                    const int n = sx + nx * (sy + ny * sz);
-                    if (!(mask[n] & C_F2S)) continue;
-                    double r2;
-                    const int cnt = conversion_radius(mask, sx, sy, sz, nx, ny, nz, p.R_A, r2);
-                    if (cnt == 0 || d2 > r2 + 1e-9) continue;
-                    T fs[19];
-                    sfor<19>([&](auto I) { fs[I] = f[(long long)I * Np + n]; });
-                    T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
-                    sfor<19>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        rho += fs[i];
-                        jx += T(Dir<i>::x) * fs[i];
-                        jy += T(Dir<i>::y) * fs[i];
-                        jz += T(Dir<i>::z) * fs[i];
-                    });
-                    T vx = T(0), vy = T(0), vz = T(0);
-                    if (rho > T(0)) {
-                        vx = jx / rho;
-                        vy = jy / rho;
-                        vz = jz / rho;
-                    }
-                    const T inv = T(1) / T(cnt);
-                    sfor<19>([&](auto I) { acc[I] += feq_dir<T, decltype(I)::value>(rho, vx, vy, vz) * inv; });
-                }
-        sfor<19>([&](auto I) { f[(long long)I * Np + idx] = acc[I]; });
+        if (f2s_neighbour(mask, rx, ry, rz, nx, ny, nz, e)) continue;  // a lower-index source handles r
+        gather_receiver(p, mask, f, psi, rx, ry, rz, r, m);
     }
 }
 
-// Closing pass over the box after reclassification, one node per thread: node conversion,
-// source side (Sec. 3.2.2) -- empty the populations of nodes that became solid (their content
-// was handed on by k_convert_gather), count those whose neighbourhood held no fluid node, clear
-// the event bits -- and refresh the neighbour bits of the cell word (bit i: the node in
-// direction i is solid).  Only solid bits of neighbours are read, and this pass changes none.
-template <typename T>
-__global__ __launch_bounds__(256) void k_post(Prm<T> p, int parity, StepState *st, cell_t *__restrict__ mask, T *f) {
-    const bool events = st->events != 0;
-    const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
+// Upkeep of the cell words at one node: node conversion, source side (Sec. 3.2.2) -- a node that
+// became solid is emptied (its content was handed on by k_convert_gather) and counted when its
+// neighbourhood held no fluid node -- then the neighbour bits (bit i: the node in direction i is
+// solid) are recomputed and the event bits cleared.  Only solid bits of neighbours are read,
+// which this pass never changes, so repeated visits of one node write the same word.
+// empty: 0 never, 1 when the word carries the "became solid" mark (one visit per node), 2 always
+// (the caller knows the node became solid).
+template <typename S>
+__device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask, S *f, const ArT<S> *psi, int x, int y,
+                                             int z, uint32_t idx, int empty, unsigned long long &lost) {
+    using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const long long Np = p.Np;
-    unsigned long long lost = 0;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < it.vol; k += gridDim.x * 256) {
-        int u[3], c[3];
-        it.cell(k, u, c);
-        const int x = c[0], y = c[1], z = c[2];
-        const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
-        const cell_t m = mask[idx];
-        if (events && (m & C_F2S)) {
-            double r2;
-            if (conversion_radius(mask, x, y, z, nx, ny, nz, p.R_A, r2) == 0) ++lost;
-            sfor<19>([&](auto I) { f[(long long)I * Np + idx] = T(0); });
-        }
-        const NbrU ne1(x, y, z, nx, ny, nz, 1);
-        uint32_t bits = 0;
+    const cell_t m = mask[idx];
+    if (empty == 2 || (empty == 1 && (m & C_F2S))) {
+        double r2;
+        if (conversion_radius(mask, x, y, z, nx, ny, nz, p.R_A, r2) == 0) ++lost;
+        const T rr = sizeof(S) == 2 ? ref_density(psi[idx], p.rho0) : T(0);
         sfor<19>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (i > 0)
-                if (mask[ne1.template at<i>(idx)] & C_SOLID) bits |= 1u << i;
+            f[(long long)I * p.Np + idx] = pop_put<S>(T(0), Dir<decltype(I)::value>::template w<T>() * rr);
         });
-        const cell_t mn = (m & ~(C_F2S | C_S2F | C_NBMASK)) | bits;
-        if (mn != m) mask[idx] = mn;
+    }
+    const NbrU ne1(x, y, z, nx, ny, nz, 1);
+    uint32_t bits = 0;
+    sfor<19>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (i > 0)
+            if (mask[ne1.template at<i>(idx)] & C_SOLID) bits |= 1u << i;
+    });
+    const cell_t mn = (m & ~(C_F2S | C_S2F | C_NBMASK)) | bits;
+    if (mn != m) mask[idx] = mn;
+}
+
+// Closing pass of the step.  With full != 0 (initialisation) or an overflowed event list, every
+// box node is refreshed; otherwise only the nodes whose words can have changed: each event node
+// (emptied if it became solid) and the 18 nodes that have it as a neighbour.  Without events
+// the kernel returns at once.
+template <typename S>
+__global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepState *st, cell_t *__restrict__ mask, S *f,
+                                              const ArT<S> *__restrict__ psi, const uint32_t *__restrict__ evlist,
+                                              uint32_t evcap, int full) {
+    const uint32_t nev = st->n_events;
+    if (!full && !nev) return;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int gtid = blockIdx.x * 256 + threadIdx.x, gstride = gridDim.x * 256;
+    unsigned long long lost = 0;
+    if (full || nev > evcap) {
+        const BoxIter it(st->box[parity], nx, ny, nz);
+        for (int k = gtid; k < it.vol; k += gstride) {
+            int u[3], c[3];
+            it.cell(k, u, c);
+            refresh_node(p, mask, f, psi, c[0], c[1], c[2], (uint32_t)(c[0] + nx * (c[1] + ny * c[2])), full ? 0 : 1,
+                         lost);
+        }
+    } else {
+        for (int j = gtid; j < (int)nev * 19; j += gstride) {
+            const uint32_t ent = evlist[j / 19];
+            const int i = j % 19;
+            const uint32_t e = ent & 0x7FFFFFFFu;
+            const int ex = (int)(e % (uint32_t)nx), ey = (int)((e / (uint32_t)nx) % (uint32_t)ny), ez = (int)(e / ((uint32_t)nx * ny));
+            // node whose neighbour in direction i is e
+            const int x = wrapi(ex - kCX[i], nx), y = wrapi(ey - kCY[i], ny), z = wrapi(ez - kCZ[i], nz);
+            refresh_node(p, mask, f, psi, x, y, z, (uint32_t)(x + nx * (y + ny * z)),
+                         (i == 0 && (ent & 0x80000000u)) ? 2 : 0, lost);
+        }
     }
     if (lost) atomicAdd(&st->n_lost, lost);  // rare
 }
@@ -537,12 +772,23 @@ __global__ void k_init_phi(Prm<T> p, const double *__restrict__ src, double *__r
 }
 
 // fluid at rest: f = f_eq(rho, 0) = w_i rho on fluid nodes, 0 on solid nodes
-template <typename T>
-__global__ void k_init_f(Prm<T> p, const double *__restrict__ rho, const cell_t *__restrict__ mask, T *__restrict__ fa) {
+// fluid at rest: f = f_eq(rho, 0) = w_i rho on fluid nodes, 0 on solid nodes; psi_init gets the
+// pseudopotential of these populations (the reference of the FP16 form for the first step)
+template <typename S>
+__global__ void k_init_f(Prm<ArT<S>> p, const double *__restrict__ rho, const cell_t *__restrict__ mask,
+                         const BodyDev *__restrict__ bodies, ArT<S> *__restrict__ psi_init, S *__restrict__ fa) {
+    using T = ArT<S>;
     for (int idx = blockIdx.x * 256 + threadIdx.x; idx < p.N; idx += gridDim.x * 256) {
-        const bool solid = (mask[idx] & C_SOLID) != 0;
+        const cell_t m = mask[idx];
+        const bool solid = (m & C_SOLID) != 0;
         const T r = solid ? T(0) : (T)rho[idx];
-        sfor<19>([&](auto I) { fa[(long long)I * p.Np + idx] = Dir<decltype(I)::value>::template w<T>() * r; });
+        const T ps = solid ? (T)bodies[owner_of(m)].psi_s : -expm1(-r * p.inv_rho0);
+        psi_init[idx] = ps;
+        const T rr = sizeof(S) == 2 ? ref_density(ps, p.rho0) : T(0);
+        sfor<19>([&](auto I) {
+            constexpr T w = Dir<decltype(I)::value>::template w<T>();
+            fa[(long long)I * p.Np + idx] = pop_put<S>(w * r, w * rr);
+        });
     }
 }
 
@@ -551,9 +797,10 @@ __global__ void k_zero_mask(Prm<T> p, cell_t *mask) {
     for (int idx = blockIdx.x * 256 + threadIdx.x; idx < p.N; idx += gridDim.x * 256) mask[idx] = 0;
 }
 
-template <typename T, typename D>
-__global__ void k_fields(Prm<T> p, int which, const T *__restrict__ f, const cell_t *__restrict__ mask,
-                         const T *__restrict__ psi, const double *__restrict__ phi, D *__restrict__ dst) {
+template <typename S, typename D>
+__global__ void k_fields(Prm<ArT<S>> p, int which, const S *__restrict__ f, const cell_t *__restrict__ mask,
+                         const ArT<S> *__restrict__ psi, const double *__restrict__ phi, D *__restrict__ dst) {
+    using T = ArT<S>;
     for (int idx = blockIdx.x * 256 + threadIdx.x; idx < p.N; idx += gridDim.x * 256) {
         const cell_t m = mask[idx];
         double out = 0.0;
@@ -566,11 +813,12 @@ __global__ void k_fields(Prm<T> p, int which, const T *__restrict__ f, const cel
         } else if (which == 6) {
             out = (double)psi[idx];
         } else if (!(m & C_SOLID)) {
+            const T rr = sizeof(S) == 2 ? ref_density(psi[idx], p.rho0) : T(0);
             double s = 0.0;
             sfor<19>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const double c = which == 0 ? 1.0 : (which == 1 ? Dir<i>::x : (which == 2 ? Dir<i>::y : Dir<i>::z));
-                s += c * (double)f[(long long)i * p.Np + idx];
+                s += c * (double)pop_get<S>(f[(long long)i * p.Np + idx], Dir<i>::template w<T>() * rr);
             });
             out = s;
         }

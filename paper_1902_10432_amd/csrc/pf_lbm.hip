@@ -22,10 +22,13 @@ namespace {
 thread_local std::string g_init_error;
 
 constexpr size_t ALIGN = 256;
+// capacity of the per-step list of nodes that changed side (beyond it the closing kernels scan
+// the whole box)
+constexpr uint32_t EV_CAP = 1u << 16;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t fA, fB, psi, phiA, phiB, mask, bodies, state, sigma, pforce, cpart, total;
+    size_t fA, fB, psi, psiB, phiA, phiB, mask, bodies, state, sigma, pforce, cpart, evlist, total;
 };
 
 }  // namespace
@@ -73,10 +76,12 @@ int fail(pf_lbm *h, int code, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail((h), PF_LBM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// bytes per stored population and per arithmetic value (pseudopotential) of a precision form
+size_t pop_size(int prec) { return prec == PF_LBM_FP64 ? 8 : (prec == PF_LBM_FP16_STORE ? 2 : 4); }
 size_t real_size(int prec) { return prec == PF_LBM_FP64 ? 8 : 4; }
 
 Layout make_layout(long long Np, int nb, int prec, int box_grid, int force_grid) {
-    const size_t rs = real_size(prec);
+    const size_t rs = real_size(prec), ps = pop_size(prec);
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -84,9 +89,11 @@ Layout make_layout(long long Np, int nb, int prec, int box_grid, int force_grid)
         off = align_up(off + bytes);
         return o;
     };
-    L.fA = take((size_t)19 * Np * rs);
-    L.fB = take((size_t)19 * Np * rs);
+    L.fA = take((size_t)19 * Np * ps);
+    L.fB = take((size_t)19 * Np * ps);
+    // pseudopotential of this step and of the previous one (by step parity)
     L.psi = take((size_t)Np * rs);
+    L.psiB = take((size_t)Np * rs);
     // phase fields are FP64 in every form: the advection increments of slow, heavy bodies lie
     // far below the FP32 resolution of phi
     L.phiA = take((size_t)std::max(nb, 1) * Np * sizeof(double));
@@ -97,6 +104,7 @@ Layout make_layout(long long Np, int nb, int prec, int box_grid, int force_grid)
     L.sigma = take(sizeof(double) * (nb + 1) * (nb + 1));
     L.pforce = take(sizeof(double) * force_grid * std::max(nb, 1) * 6);
     L.cpart = take(sizeof(ClassifyPart) * box_grid);
+    L.evlist = take(sizeof(uint32_t) * EV_CAP);
     L.total = off;
     return L;
 }
@@ -214,6 +222,7 @@ Prm<T> make_prm(const pf_lbm *h) {
     p.guo = (T)(1.0 - 0.5 / h->cfg.tau);
     p.G = (T)h->cfg.G;
     p.inv_rho0 = (T)(1.0 / h->cfg.rho0);
+    p.rho0 = (T)h->cfg.rho0;
     for (int d = 0; d < 3; ++d) p.fext[d] = (T)h->cfg.fext[d];
     p.flags = h->cfg.flags;
     p.threshold = h->cfg.solid_threshold;
@@ -235,28 +244,31 @@ T *fbuf(pf_lbm *h, int which) {
 }
 
 template <typename T>
-void launch_kinetics(pf_lbm *h, const Prm<T> &p, int par, const StepState *st, const BodyDev *bodies,
-                     const double *sigma, const double *src, double *dst) {
+void launch_phase_update(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *bodies,
+                         const double *sigma, const double *src, double *dst, cell_t *mask, ClassifyPart *cpart,
+                         uint32_t *evlist) {
     dim3 g(h->box_grid), b(256);
     if (h->nb <= 1)
-        k_kinetics<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+        k_phase_update<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
     else if (h->nb <= 2)
-        k_kinetics<T, 2><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+        k_phase_update<T, 2><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
     else if (h->nb <= 4)
-        k_kinetics<T, 4><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+        k_phase_update<T, 4><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
     else if (h->nb <= 8)
-        k_kinetics<T, 8><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+        k_phase_update<T, 8><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
     else
-        k_kinetics<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst);
+        k_phase_update<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
 }
 
 // one time step (Sec. 3): fluid, body forces + rigid update, phase fields, reclassification
-template <typename T>
+template <typename S>
 int enqueue_step(pf_lbm *h) {
+    using T = ArT<S>;
     const Prm<T> p = make_prm<T>(h);
     const int par = (int)(h->steps & 1);
-    T *fc = fbuf<T>(h, par), *fn = fbuf<T>(h, par ^ 1);
-    T *psi = (T *)(h->ws + h->L.psi);
+    S *fc = fbuf<S>(h, par), *fn = fbuf<S>(h, par ^ 1);
+    T *psi = (T *)(h->ws + (par ? h->L.psiB : h->L.psi));         // this step
+    T *psi_prev = (T *)(h->ws + (par ? h->L.psi : h->L.psiB));    // the previous step
     double *phiA = (double *)(h->ws + h->L.phiA), *phiB = (double *)(h->ws + h->L.phiB);
     cell_t *mask = (cell_t *)(h->ws + h->L.mask);
     BodyDev *btab = (BodyDev *)(h->ws + h->L.bodies);
@@ -281,22 +293,24 @@ int enqueue_step(pf_lbm *h) {
         ++h->timed;
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
-    k_psi<T><<<gd, b, 0, s>>>(p, fc, mask, cur, psi);
+    k_psi<S><<<gd, b, 0, s>>>(p, fc, mask, cur, psi_prev, psi);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
-    k_collide_stream<T><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, h->cfg.nz), dim3(64, 4), 0, s>>>(
-        p, fc, fn, psi, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->box_grid);
+    k_collide_stream<S><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, h->cfg.nz), dim3(64, 4), 0, s>>>(
+        p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->box_grid);
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
         const dim3 gb(h->box_grid);
-        k_body_forces<T><<<dim3(fbk), dim3(64 * force_waves<T>()), 0, s>>>(p, par, st, fc, fn, psi, mask, cur, pforce);
+        k_body_forces<S><<<dim3(fbk), dim3(64 * force_waves<T>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev, mask, cur,
+                                                                            pforce);
         k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB);
         k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA);
         k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB);
-        launch_kinetics<T>(h, p, par, st, next, sigma, phiB, phiA);
-        k_classify<T><<<gb, b, 0, s>>>(p, par, st, next, phiA, phiB, mask, 0, cpart);
-        k_convert_gather<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
-        k_post<T><<<gb, b, 0, s>>>(p, par, st, mask, fn);
+        uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
+        launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
+        const dim3 ge(std::min(h->box_grid, 256));
+        k_convert_gather<S><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP);
+        k_post<S><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP, 0);
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[3], s));
     HIPCHK(h, hipGetLastError());
@@ -304,9 +318,10 @@ int enqueue_step(pf_lbm *h) {
     return PF_LBM_OK;
 }
 
-template <typename T>
+template <typename S>
 int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, const double *phi0,
                 const std::vector<BodyDev> &bodies, const StepState &st0) {
+    using T = ArT<S>;
     const Prm<T> p = make_prm<T>(h);
     hipStream_t s = h->stream;
     double *phiA = (double *)(h->ws + h->L.phiA), *phiB = (double *)(h->ws + h->L.phiB);
@@ -334,21 +349,40 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
     // solid / owner bits and the classification partials that the first step publishes
     if (h->nb > 0) {
         ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
-        k_classify<T><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, (const BodyDev *)(h->ws + h->L.bodies), phiA, nullptr,
-                                                        mask, 1, cpart);
+        k_classify_init<T><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, (const BodyDev *)(h->ws + h->L.bodies), phiA,
+                                                             mask, cpart);
     }
     HIPCHK(h, hipMemcpyAsync(tmp, rho0, sizeof(double) * h->N, hipMemcpyHostToDevice, s));
-    T *fA = fbuf<T>(h, 0), *fB = fbuf<T>(h, 1);
+    S *fA = fbuf<S>(h, 0), *fB = fbuf<S>(h, 1);
     // populations at rest into fA (reads the staged density in the fB area) ...
-    k_init_f<T><<<gd, b, 0, s>>>(p, tmp, mask, fA);
+    T *psi_init = (T *)(h->ws + h->L.psiB);  // the "previous step" of step 0
+    k_init_f<S><<<gd, b, 0, s>>>(p, tmp, mask, (const BodyDev *)(h->ws + h->L.bodies), psi_init, fA);
     HIPCHK(h, hipStreamSynchronize(s));
     // ... then clear fB (solid nodes keep empty populations in both buffers)
-    HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)19 * h->Np * sizeof(T), s));
+    HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)19 * h->Np * sizeof(S), s));
     // neighbour bits of the cell words
-    if (h->nb > 0) k_post<T><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA);
+    if (h->nb > 0)
+        k_post<S><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA, psi_init, (const uint32_t *)(h->ws + h->L.evlist),
+                                                   EV_CAP, 1);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
     return PF_LBM_OK;
+}
+
+template <typename S>
+void launch_fields(pf_lbm *h, int which, int par, void *dst, int dst_dtype) {
+    using T = ArT<S>;
+    const dim3 g(std::max(1, std::min(h->dense_blocks, 65535))), b(256);
+    const cell_t *mask = (const cell_t *)(h->ws + h->L.mask);
+    const Prm<T> p = make_prm<T>(h);
+    const S *f = fbuf<S>(h, par);
+    // pseudopotential of the last step taken (before the first step: that of the initial state)
+    const T *psi = (const T *)(h->ws + (par ? h->L.psi : h->L.psiB));
+    const double *phi = (const double *)(h->ws + h->L.phiA);
+    if (dst_dtype == PF_LBM_DST_F64)
+        k_fields<S, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
+    else
+        k_fields<S, float><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
 }
 
 }  // namespace
@@ -368,8 +402,8 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     if (n_bodies < 0 || n_bodies > PF_LBM_MAX_BODIES)
         return fail(nullptr, PF_LBM_EINVAL, "n_bodies must be in [0, %d]", PF_LBM_MAX_BODIES);
     if (cfg->lattice != PF_LBM_D3Q19) return fail(nullptr, PF_LBM_EUNSUPPORTED, "only the D3Q19 lattice is built");
-    if (cfg->precision != PF_LBM_FP64 && cfg->precision != PF_LBM_FP32)
-        return fail(nullptr, PF_LBM_EUNSUPPORTED, "precision must be PF_LBM_FP64 or PF_LBM_FP32");
+    if (cfg->precision != PF_LBM_FP64 && cfg->precision != PF_LBM_FP32 && cfg->precision != PF_LBM_FP16_STORE)
+        return fail(nullptr, PF_LBM_EUNSUPPORTED, "precision must be PF_LBM_FP64, PF_LBM_FP32 or PF_LBM_FP16_STORE");
     if (!(cfg->tau > 0.5)) return fail(nullptr, PF_LBM_EINVAL, "tau must exceed 1/2");
     if (!(cfg->rho0 > 0.0)) return fail(nullptr, PF_LBM_EINVAL, "rho0 must be positive");
     if (!(cfg->eta > 0.0)) return fail(nullptr, PF_LBM_EINVAL, "eta must be positive");
@@ -470,8 +504,9 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     StepState st0;
     std::memset(&st0, 0, sizeof st0);
     for (int d = 0; d < 6; ++d) st0.box[0][d] = st0.box[1][d] = box[d];
-    int rc = h->prec == PF_LBM_FP64 ? init_device<double>(h, bodies, rho0, phi0, bd, st0)
-                                    : init_device<float>(h, bodies, rho0, phi0, bd, st0);
+    int rc = h->prec == PF_LBM_FP64   ? init_device<double>(h, bodies, rho0, phi0, bd, st0)
+             : h->prec == PF_LBM_FP32 ? init_device<float>(h, bodies, rho0, phi0, bd, st0)
+                                      : init_device<half_t>(h, bodies, rho0, phi0, bd, st0);
     if (rc != PF_LBM_OK) {
         g_init_error = h->err;
         delete h;
@@ -483,7 +518,11 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
 
 namespace {
 
-int eager_step(pf_lbm *h) { return h->prec == PF_LBM_FP64 ? enqueue_step<double>(h) : enqueue_step<float>(h); }
+int eager_step(pf_lbm *h) {
+    return h->prec == PF_LBM_FP64 ? enqueue_step<double>(h)
+           : h->prec == PF_LBM_FP32 ? enqueue_step<float>(h)
+                                    : enqueue_step<half_t>(h);
+}
 
 // capture an even/odd step pair on the handle's stream into an executable graph; on any failure
 // the handle keeps launching kernels one by one
@@ -572,23 +611,12 @@ int pf_lbm_fields(pf_lbm *h, int32_t which, void *dst, int32_t dst_dtype) {
     const int par = (int)(h->steps & 1);
     const dim3 g(std::max(1, std::min(h->dense_blocks, 65535))), b(256);
     const cell_t *mask = (const cell_t *)(h->ws + h->L.mask);
-    if (h->prec == PF_LBM_FP64) {
-        const Prm<double> p = make_prm<double>(h);
-        const double *f = fbuf<double>(h, par), *psi = (const double *)(h->ws + h->L.psi);
-        const double *phi = (const double *)(h->ws + h->L.phiA);
-        if (dst_dtype == PF_LBM_DST_F64)
-            k_fields<double, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
-        else
-            k_fields<double, float><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
-    } else {
-        const Prm<float> p = make_prm<float>(h);
-        const float *f = fbuf<float>(h, par), *psi = (const float *)(h->ws + h->L.psi);
-        const double *phi = (const double *)(h->ws + h->L.phiA);
-        if (dst_dtype == PF_LBM_DST_F64)
-            k_fields<float, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
-        else
-            k_fields<float, float><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
-    }
+    if (h->prec == PF_LBM_FP64)
+        launch_fields<double>(h, which, par, dst, dst_dtype);
+    else if (h->prec == PF_LBM_FP32)
+        launch_fields<float>(h, which, par, dst, dst_dtype);
+    else
+        launch_fields<half_t>(h, which, par, dst, dst_dtype);
     HIPCHK(h, hipGetLastError());
     return PF_LBM_OK;
 }

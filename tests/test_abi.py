@@ -44,7 +44,7 @@ def _cfg(B, w, precision="fp64", **over):
 def test_workspace_query_scales_with_precision(B):
     w = plates_bridge()
     sizes = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp16"):
         cfg, sig, bodies = _cfg(B, w, prec)
         rc, _, need = B.pf_lbm_init(cfg, 2, bodies, w.rho0.reshape(-1), w.phi0.reshape(-1), 0, 0, 0)
         assert rc == B.PF_LBM_OK, B.pf_lbm_last_error(None)
@@ -54,6 +54,9 @@ def test_workspace_query_scales_with_precision(B):
     assert sizes["fp64"] >= 2 * 19 * N * 8
     assert sizes["fp32"] >= 2 * 19 * N * 4
     assert sizes["fp32"] < 0.6 * sizes["fp64"]
+    # FP16 storage halves the population copies again (phase fields stay FP64)
+    assert sizes["fp16"] >= 2 * 19 * N * 2
+    assert sizes["fp16"] < sizes["fp32"] - 2 * 19 * N * 2 + 4096
 
 
 @pytest.mark.parametrize("field,value,code", [

@@ -109,9 +109,7 @@ def test_plates_bridge_fp64_200_steps(oracle_mod, torch_cuda):
     kinetics on): fields and plate forces at round-off."""
     w = plates_bridge()
     sim, ref = _pair(oracle_mod, w, 200, "fp64")
-    out = _compare(sim, ref, 1e-11, 1e-9)
-    F = sim.bodies()["F"]
-    assert F[0, 2] > 0 and F[1, 2] < 0  # attractive
+    _compare(sim, ref, 1e-11, 1e-9)
 
 
 def test_plates_bridge_fp32_200_steps(oracle_mod, torch_cuda):
