@@ -147,269 +147,302 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
     if (cfl) atomicOr(&st->err, 2u);  // rare: only when the input breaks the CFL bound
 }
 
-// Classification of one node from its final phase values (Sec. 3.2.2): solid iff the fluid
-// fraction 1 - sum phi is below the threshold, owner = argmax phi (lowest index on ties).
-template <int NBMAX>
-__device__ __forceinline__ void classify_node(const double *phi_a, int nbod, double threshold, bool &solid, int &arg,
-                                              double &sum) {
-    double best = -1.0;
-    sum = 0.0;
-    arg = 0;
+// Multi-phase-field kinetics at one node (Sec. 3.3), explicit Euler: v[a] are the advected solid
+// phases at the node, nbv(e, a) the value of phase a at face neighbour e (0..5); phase 0 = fluid
+// = 1 - sum of solids.  For nodes where at least two phases are active (above the floor at the
+// node or a face neighbour):
+//   dphi_a/dt = sum_{b active, b != a} (M/N) ( sigma_ab (I_a - I_b)
+//               + sum_{g active, g != a, b} (sigma_bg - sigma_ag) I_g + pi^2/(4 eta) (h_a - h_b) ),
+// I = lap(phi) + (pi^2/eta^2) phi with the 7-point Laplacian, h_fluid = 0 and h_a the volume
+// driving term (set at the start of the step from the phase fields before advection, which
+// leaves the volumes unchanged); then each solid phase is clipped to [0, 1] (values below the
+// floor to 0) and the solids are rescaled if their sum exceeds 1.  sg: (NBMAX+1)^2 interface
+// energies, hh: driving terms with hh[0] = 0.
+template <int NBMAX, typename NbrF>
+__device__ __forceinline__ void kinetics_node(const double *v, NbrF nbv, int nbod, const double *sg, const double *hh,
+                                              double mu, double vterm, double M, double *out) {
+    using T = double;
+    constexpr int NP = NBMAX + 1;
+    T v0[NP];
+    T sum0 = T(0);
 #pragma unroll
     for (int a = 0; a < NBMAX; ++a) {
-        if (a >= nbod) break;
-        const double v = phi_a[a];
-        sum += v;
-        if (v > best) {
-            best = v;
-            arg = a;
-        }
+        v0[a + 1] = v[a];
+        sum0 += v[a];
     }
-    solid = nbod > 0 && (1.0 - sum) < threshold;
+    v0[0] = T(1) - sum0;
+    T lap[NP];
+    bool on[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        lap[q] = T(-6) * v0[q];
+        on[q] = v0[q] > T(PHI_FLOOR);
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < NBMAX; ++a) {
+            const T w = nbv(e, a);
+            s += w;
+            lap[a + 1] += w;
+            on[a + 1] = on[a + 1] || w > T(PHI_FLOOR);
+        }
+        const T vf = T(1) - s;
+        lap[0] += vf;
+        on[0] = on[0] || vf > T(PHI_FLOOR);
+    }
+    int na = 0;
+    T I[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        if (q > nbod) on[q] = false;
+        I[q] = lap[q] + mu * v0[q];
+        na += on[q] ? 1 : 0;
+    }
+    T tot = T(0);
+#pragma unroll
+    for (int a = 1; a < NP; ++a) {
+        T nv = v0[a];
+        if (na >= 2 && on[a]) {
+            T rate = T(0);
+#pragma unroll
+            for (int b = 0; b < NP; ++b) {
+                if (b == a || !on[b]) continue;
+                T t = sg[a * NP + b] * (I[a] - I[b]);
+#pragma unroll
+                for (int g = 0; g < NP; ++g) {
+                    if (g == a || g == b || !on[g]) continue;
+                    t += (sg[b * NP + g] - sg[a * NP + g]) * I[g];
+                }
+                t += vterm * (hh[a] - hh[b]);
+                rate += (M / T(na)) * t;
+            }
+            nv = v0[a] + rate;
+        }
+        nv = nv < T(PHI_FLOOR) ? T(0) : (nv > T(1) ? T(1) : nv);
+        out[a - 1] = nv;
+        tot += nv;
+    }
+    if (tot > T(1)) {
+#pragma unroll
+        for (int a = 0; a < NBMAX; ++a) out[a] /= tot;
+    }
 }
 
-// Phase-field update of the step after the advection sweeps, one box node per thread:
-//  * multi-phase-field kinetics (Sec. 3.3), explicit Euler, for nodes where at least two phases
-//    are active (above the floor at the node or a face neighbour; phase 0 = fluid = 1 - sum of
-//    solids):
-//      dphi_a/dt = sum_{b active, b != a} (M/N) ( sigma_ab (I_a - I_b)
-//                  + sum_{g active, g != a, b} (sigma_bg - sigma_ag) I_g + pi^2/(4 eta) (h_a - h_b) ),
-//    I = lap(phi) + (pi^2/eta^2) phi with the 7-point Laplacian, h_fluid = 0 and h_a the volume
-//    driving term of the body table (set at the start of the step from the phase fields before
-//    advection, which leaves the volumes unchanged); then each solid phase is clipped to [0, 1]
-//    (values below the floor to 0) and the solids are rescaled if their sum exceeds 1; without
-//    kinetics the phase values pass unchanged;
-//  * reclassification of the node (Sec. 3.2.2) and, for a node that changed side (rare), an
-//    entry in the step's event list: cell index, bit 31 set when it became solid;
-//  * per-block results for the next step (publish_step_state): support bounds in unwrapped
-//    coordinates, per-body solid radius, sum of phi and count of interface nodes.
-// Face neighbours outside the box hold no phase and are not read.
+// Reclassification of the nodes of a phase update and the per-block results the next step
+// publishes (publish_step_state): support bounds (unwrapped coordinates), conversion counts,
+// per-body solid radius, sum of phi and count of interface nodes floor < phi < 1.
+template <int NBMAX>
+struct ClassAcc {
+    int lo[3], hi[3];
+    uint32_t f2s, s2f;
+    float rad[NBMAX];
+    double vol[NBMAX];
+    uint32_t icnt[NBMAX];
+
+    __device__ __forceinline__ ClassAcc() {
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = INT32_MAX;
+            hi[d] = INT32_MIN;
+        }
+        f2s = s2f = 0;
+#pragma unroll
+        for (int a = 0; a < NBMAX; ++a) {
+            rad[a] = 0.0f;
+            vol[a] = 0.0;
+            icnt[a] = 0u;
+        }
+    }
+
+    // Solid iff the fluid fraction 1 - sum phi is below the threshold, owner = argmax phi (lowest
+    // index on ties; Sec. 3.2.2).  Updates the cell word (marks a change of side) and returns the
+    // event-list entry + 1 of a node that changed side (bit 31: it became solid), else 0.
+    template <typename PT>
+    __device__ __forceinline__ uint32_t node(const Prm<PT> &p, const BodyDev *__restrict__ bodies,
+                                             cell_t *__restrict__ mask, int idx, const int *u, const int *c,
+                                             const double *out) {
+        const int nbod = p.nb;
+        double sum = 0.0, best = -1.0;
+        int arg = 0;
+#pragma unroll
+        for (int a = 0; a < NBMAX; ++a) {
+            if (a >= nbod) break;
+            sum += out[a];
+            if (out[a] > best) {
+                best = out[a];
+                arg = a;
+            }
+            vol[a] += out[a];
+            icnt[a] += (out[a] > PHI_FLOOR && out[a] < 1.0) ? 1u : 0u;
+        }
+        const bool solid = nbod > 0 && (1.0 - sum) < p.threshold;
+        uint32_t event = 0;
+        const cell_t old = mask[idx];
+        cell_t m = (old & C_NBMASK) | (solid ? solid_word(arg) : 0u);
+        if (solid && !(old & C_SOLID)) {
+            m |= C_F2S;
+            ++f2s;
+            event = ((uint32_t)idx | 0x80000000u) + 1u;
+        }
+        if (!solid && (old & C_SOLID)) {
+            m |= C_S2F;
+            ++s2f;
+            event = (uint32_t)idx + 1u;
+        }
+        if (m != old) mask[idx] = m;
+        if (solid) {
+            // distance of this solid node from its body's centre (bounds the repulsion search)
+            const BodyDev &B = bodies[arg];
+            const double rx = mimg_r(c[0] - B.X[0], p.nx, p.inv_n[0]), ry = mimg_r(c[1] - B.X[1], p.ny, p.inv_n[1]),
+                         rz = mimg_r(c[2] - B.X[2], p.nz, p.inv_n[2]);
+            const float r = (float)sqrt(rx * rx + ry * ry + rz * rz) + 1e-3f;
+#pragma unroll
+            for (int a = 0; a < NBMAX; ++a)
+                if (a == arg) rad[a] = fmaxf(rad[a], r);
+        }
+        if (sum > 0.0)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = min(lo[d], u[d]);
+                hi[d] = max(hi[d], u[d]);
+            }
+        return event;
+    }
+
+    // whole block (256 threads, uniform call): cpart[blockIdx.x] and the conversion counters
+    __device__ void finish(int nbod, StepState *st, ClassifyPart *cpart) {
+        __shared__ int32_t sb[4][6];
+        __shared__ uint32_t sc[4][2];
+        __shared__ float sr[4][NBMAX];
+        __shared__ double sv[4][NBMAX];
+        __shared__ uint32_t si[4][NBMAX];
+        const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+        for (int d = 0; d < 3; ++d) {
+            const int l = wave_min(lo[d]), h = wave_max(hi[d]);
+            if (lane == 0) {
+                sb[wave][d] = l;
+                sb[wave][3 + d] = h;
+            }
+        }
+        const uint32_t a2 = (uint32_t)wave_sum((int)f2s), b2 = (uint32_t)wave_sum((int)s2f);
+        if (lane == 0) {
+            sc[wave][0] = a2;
+            sc[wave][1] = b2;
+        }
+#pragma unroll
+        for (int a = 0; a < NBMAX; ++a) {
+            if (a >= nbod) break;
+            float r = rad[a];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
+            const double v = wave_sum(vol[a]);
+            const int ic = wave_sum((int)icnt[a]);
+            if (lane == 0) {
+                sr[wave][a] = r;
+                sv[wave][a] = v;
+                si[wave][a] = (uint32_t)ic;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            ClassifyPart cp;
+            for (int d = 0; d < 3; ++d) {
+                cp.lo[d] = min(min(sb[0][d], sb[1][d]), min(sb[2][d], sb[3][d]));
+                cp.hi[d] = max(max(sb[0][3 + d], sb[1][3 + d]), max(sb[2][3 + d], sb[3][3 + d]));
+            }
+            cp.f2s = sc[0][0] + sc[1][0] + sc[2][0] + sc[3][0];
+            cp.s2f = sc[0][1] + sc[1][1] + sc[2][1] + sc[3][1];
+            for (int b = 0; b < PF_LBM_MAX_BODIES; ++b) {
+                const bool on = b < nbod;
+                cp.srad[b] = on ? fmaxf(fmaxf(sr[0][b], sr[1][b]), fmaxf(sr[2][b], sr[3][b])) : 0.0f;
+                cp.vol[b] = on ? ((sv[0][b] + sv[1][b]) + sv[2][b]) + sv[3][b] : 0.0;
+                cp.icnt[b] = on ? si[0][b] + si[1][b] + si[2][b] + si[3][b] : 0u;
+            }
+            cpart[blockIdx.x] = cp;
+            if (cp.f2s + cp.s2f) {  // rare: nodes of this block changed side
+                atomicAdd(&st->n_f2s, (unsigned long long)cp.f2s);
+                atomicAdd(&st->n_s2f, (unsigned long long)cp.s2f);
+            }
+        }
+    }
+};
+
+// Append event-list entries (entry + 1, 0 = none) of a wave: one atomic per wave that saw a node
+// change side (rare).  Called by every lane.
+__device__ __forceinline__ void append_events(StepState *st, uint32_t *evlist, uint32_t evcap, uint32_t event) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long bal = __ballot(event != 0);
+    if (!bal) return;
+    uint32_t slot0 = 0;
+    if (lane == 0) slot0 = atomicAdd(&st->n_events, (uint32_t)__popcll(bal));
+    slot0 = __shfl(slot0, 0, 64);
+    if (event) {
+        const uint32_t slot = slot0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        if (slot < evcap) evlist[slot] = event - 1u;
+    }
+}
+
+// Phase update after the advection sweeps, one box node per thread: kinetics (kinetics_node;
+// without kinetics the phases pass unchanged), reclassification with the event list, per-block
+// partials.  Face neighbours outside the box hold no phase and are not read.
 template <typename PT, int NBMAX>
 __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, StepState *st,
                                                       const BodyDev *__restrict__ bodies,
                                                       const double *__restrict__ sigma, const double *__restrict__ src,
-                                                      double *__restrict__ dst, cell_t *__restrict__ mask, ClassifyPart *__restrict__ cpart,
-                                                      uint32_t *__restrict__ evlist, uint32_t evcap) {
-    using T = double;  // phase fields are FP64 in every precision form
+                                                      double *__restrict__ dst, cell_t *__restrict__ mask,
+                                                      ClassifyPart *__restrict__ cpart, uint32_t *__restrict__ evlist,
+                                                      uint32_t evcap) {
     constexpr int NP = NBMAX + 1;
     __shared__ double sg[NP * NP];
     __shared__ double hh[NP];
-    __shared__ int32_t sb[4][6];
-    __shared__ uint32_t sc[4][2];
-    __shared__ float sr[4][NBMAX];
-    __shared__ double sv[4][NBMAX];
-    __shared__ uint32_t si[4][NBMAX];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int nbod = p.nb, np1 = nbod + 1;
+    for (int k = tid; k < NP * NP; k += 256) sg[k] = 0.0;
+    __syncthreads();
     for (int k = tid; k < np1 * np1; k += 256) sg[(k / np1) * NP + (k % np1)] = sigma[k];
-    if (tid < np1) hh[tid] = tid == 0 ? 0.0 : bodies[tid - 1].h;
+    if (tid < NP) hh[tid] = (tid == 0 || tid > nbod) ? 0.0 : bodies[tid - 1].h;
     __syncthreads();
     const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
     const bool kin = (p.flags & PF_LBM_KINETICS) != 0;
-    const T PI = T(3.14159265358979323846);
-    const T mu = PI * PI / (T)(p.eta * p.eta);
-    const T vterm = PI * PI / (T)(4.0 * p.eta);
-    const T M = (T)p.mobility;
-    // per-thread partial results, combined per block at the end
-    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
-    uint32_t f2s = 0, s2f = 0;
-    float rad[NBMAX];
-    double vol[NBMAX];
-    uint32_t icnt[NBMAX];
-#pragma unroll
-    for (int a = 0; a < NBMAX; ++a) {
-        rad[a] = 0.0f;
-        vol[a] = 0.0;
-        icnt[a] = 0u;
-    }
+    const double PI = 3.14159265358979323846;
+    const double mu = PI * PI / (p.eta * p.eta), vterm = PI * PI / (4.0 * p.eta), M = p.mobility;
+    ClassAcc<NBMAX> acc;
     const int bid = xcd_block(blockIdx.x, gridDim.x);
     for (int base = bid * 256; base < it.vol; base += gridDim.x * 256) {
         const int k = base + tid;
-        uint32_t event = 0;  // list entry + 1, 0 = none
+        uint32_t event = 0;
         if (k < it.vol) {
             int u[3], c[3];
             it.cell(k, u, c);
-            const int x = c[0], y = c[1], z = c[2];
-            const int idx = x + nx * (y + ny * z);
-            T v0[NP];
+            const int idx = c[0] + nx * (c[1] + ny * c[2]);
+            double v[NBMAX], out[NBMAX];
 #pragma unroll
-            for (int a = 0; a < NBMAX; ++a) v0[a + 1] = a < nbod ? src[(long long)a * Np + idx] : T(0);
-            T out[NP];
-#pragma unroll
-            for (int a = 1; a < NP; ++a) out[a] = v0[a];
+            for (int a = 0; a < NBMAX; ++a) {
+                v[a] = a < nbod ? src[(long long)a * Np + idx] : 0.0;
+                out[a] = v[a];
+            }
             if (kin) {
-                const Nbr nb(x, y, z, nx, ny, nz);
+                const Nbr nb(c[0], c[1], c[2], nx, ny, nz);
                 const int offs[6] = {nb.xp, nb.xm, nb.yp, nb.ym, nb.zp, nb.zm};
                 const bool ins[6] = {it.inside(0, u[0] + 1), it.inside(0, u[0] - 1), it.inside(1, u[1] + 1),
                                      it.inside(1, u[1] - 1), it.inside(2, u[2] + 1), it.inside(2, u[2] - 1)};
-                T sum0 = T(0);
-#pragma unroll
-                for (int a = 0; a < NBMAX; ++a) sum0 += v0[a + 1];
-                v0[0] = T(1) - sum0;
-                T lap[NP];
-                bool on[NP];
-#pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    lap[q] = T(-6) * v0[q];
-                    on[q] = v0[q] > T(PHI_FLOOR);
-                }
-#pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    T s = T(0);
-#pragma unroll
-                    for (int a = 0; a < NBMAX; ++a) {
-                        const T v = (a < nbod && ins[e]) ? src[(long long)a * Np + idx + offs[e]] : T(0);
-                        s += v;
-                        lap[a + 1] += v;
-                        on[a + 1] = on[a + 1] || v > T(PHI_FLOOR);
-                    }
-                    const T vf = T(1) - s;
-                    lap[0] += vf;
-                    on[0] = on[0] || vf > T(PHI_FLOOR);
-                }
-                int na = 0;
-                T I[NP];
-#pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    if (q > nbod) on[q] = false;
-                    I[q] = lap[q] + mu * v0[q];
-                    na += on[q] ? 1 : 0;
-                }
-                T tot = T(0);
-#pragma unroll
-                for (int a = 1; a < NP; ++a) {
-                    T nv = v0[a];
-                    if (na >= 2 && on[a]) {
-                        T rate = T(0);
-#pragma unroll
-                        for (int b = 0; b < NP; ++b) {
-                            if (b == a || !on[b]) continue;
-                            T t = (T)sg[a * NP + b] * (I[a] - I[b]);
-#pragma unroll
-                            for (int g = 0; g < NP; ++g) {
-                                if (g == a || g == b || !on[g]) continue;
-                                t += ((T)sg[b * NP + g] - (T)sg[a * NP + g]) * I[g];
-                            }
-                            t += vterm * (T)(hh[a] - hh[b]);
-                            rate += (M / T(na)) * t;
-                        }
-                        nv = v0[a] + rate;
-                    }
-                    nv = nv < T(PHI_FLOOR) ? T(0) : (nv > T(1) ? T(1) : nv);
-                    out[a] = nv;
-                    tot += nv;
-                }
-                if (tot > T(1)) {
-#pragma unroll
-                    for (int a = 1; a < NP; ++a) out[a] /= tot;
-                }
+                kinetics_node<NBMAX>(
+                    v,
+                    [&](int e, int a) {
+                        return (a < nbod && ins[e]) ? src[(long long)a * Np + idx + offs[e]] : 0.0;
+                    },
+                    nbod, sg, hh, mu, vterm, M, out);
             }
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a)
-                if (a < nbod) dst[(long long)a * Np + idx] = out[a + 1];
-            // reclassification
-            bool solid;
-            int arg;
-            double sum;
-            classify_node<NBMAX>(out + 1, nbod, p.threshold, solid, arg, sum);
-            const cell_t old = mask[idx];
-            cell_t m = (old & C_NBMASK) | (solid ? solid_word(arg) : 0u);
-            if (solid && !(old & C_SOLID)) {
-                m |= C_F2S;
-                ++f2s;
-                event = ((uint32_t)idx | 0x80000000u) + 1u;
-            }
-            if (!solid && (old & C_SOLID)) {
-                m |= C_S2F;
-                ++s2f;
-                event = (uint32_t)idx + 1u;
-            }
-            if (m != old) mask[idx] = m;
-#pragma unroll
-            for (int a = 0; a < NBMAX; ++a) {
-                if (a >= nbod) break;
-                vol[a] += out[a + 1];
-                icnt[a] += (out[a + 1] > PHI_FLOOR && out[a + 1] < 1.0) ? 1u : 0u;
-            }
-            if (solid) {
-                // distance of this solid node from its body's centre (bounds the repulsion search)
-                const BodyDev &B = bodies[arg];
-                const double rx = mimg_r(x - B.X[0], nx, p.inv_n[0]), ry = mimg_r(y - B.X[1], ny, p.inv_n[1]),
-                             rz = mimg_r(z - B.X[2], nz, p.inv_n[2]);
-                const float r = (float)sqrt(rx * rx + ry * ry + rz * rz) + 1e-3f;
-#pragma unroll
-                for (int a = 0; a < NBMAX; ++a)
-                    if (a == arg) rad[a] = fmaxf(rad[a], r);
-            }
-            if (sum > 0.0) {
-                for (int d = 0; d < 3; ++d) {
-                    lo[d] = min(lo[d], u[d]);
-                    hi[d] = max(hi[d], u[d]);
-                }
-            }
+                if (a < nbod) dst[(long long)a * Np + idx] = out[a];
+            event = acc.node(p, bodies, mask, idx, u, c, out);
         }
-        // event list: one atomic per wave that saw a node change side (rare)
-        const unsigned long long bal = __ballot(event != 0);
-        if (bal) {
-            uint32_t slot0 = 0;
-            if (lane == 0) slot0 = atomicAdd(&st->n_events, (uint32_t)__popcll(bal));
-            slot0 = __shfl(slot0, 0, 64);
-            if (event) {
-                const uint32_t slot = slot0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                if (slot < evcap) evlist[slot] = event - 1u;
-            }
-        }
+        append_events(st, evlist, evcap, event);
     }
-    // block results
-    for (int d = 0; d < 3; ++d) {
-        const int l = wave_min(lo[d]), h = wave_max(hi[d]);
-        if (lane == 0) {
-            sb[wave][d] = l;
-            sb[wave][3 + d] = h;
-        }
-    }
-    const uint32_t a2 = (uint32_t)wave_sum((int)f2s), b2 = (uint32_t)wave_sum((int)s2f);
-    if (lane == 0) {
-        sc[wave][0] = a2;
-        sc[wave][1] = b2;
-    }
-#pragma unroll
-    for (int a = 0; a < NBMAX; ++a) {
-        if (a >= nbod) break;
-        float r = rad[a];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
-        const double v = wave_sum(vol[a]);
-        const int ic = wave_sum((int)icnt[a]);
-        if (lane == 0) {
-            sr[wave][a] = r;
-            sv[wave][a] = v;
-            si[wave][a] = (uint32_t)ic;
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        ClassifyPart cp;
-        for (int d = 0; d < 3; ++d) {
-            cp.lo[d] = min(min(sb[0][d], sb[1][d]), min(sb[2][d], sb[3][d]));
-            cp.hi[d] = max(max(sb[0][3 + d], sb[1][3 + d]), max(sb[2][3 + d], sb[3][3 + d]));
-        }
-        cp.f2s = sc[0][0] + sc[1][0] + sc[2][0] + sc[3][0];
-        cp.s2f = sc[0][1] + sc[1][1] + sc[2][1] + sc[3][1];
-        for (int b = 0; b < PF_LBM_MAX_BODIES; ++b) {
-            const bool on = b < nbod;
-            cp.srad[b] = on ? fmaxf(fmaxf(sr[0][b], sr[1][b]), fmaxf(sr[2][b], sr[3][b])) : 0.0f;
-            cp.vol[b] = on ? ((sv[0][b] + sv[1][b]) + sv[2][b]) + sv[3][b] : 0.0;
-            cp.icnt[b] = on ? si[0][b] + si[1][b] + si[2][b] + si[3][b] : 0u;
-        }
-        cpart[blockIdx.x] = cp;
-        if (cp.f2s + cp.s2f) {  // rare: nodes of this block changed side
-            atomicAdd(&st->n_f2s, (unsigned long long)cp.f2s);
-            atomicAdd(&st->n_s2f, (unsigned long long)cp.s2f);
-        }
-    }
+    acc.finish(nbod, st, cpart);
 }
 
 // Classification of the initial phase fields (Sec. 3.2.2): solid iff the fluid fraction

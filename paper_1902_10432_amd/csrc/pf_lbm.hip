@@ -43,6 +43,7 @@ struct pf_lbm {
     long long N = 0, Np = 0;
     int dense_blocks = 0, box_blocks = 1;
     int box_grid = 1, force_grid = 1;  // grids of the box kernels and of the force scan
+    int cgrid = 1;  // classification partials written per step (grid of the phase update)
     long long steps = 0;
     std::vector<double> sigma;
     std::string err;
@@ -80,7 +81,7 @@ int fail(pf_lbm *h, int code, const char *fmt, ...) {
 size_t pop_size(int prec) { return prec == PF_LBM_FP64 ? 8 : (prec == PF_LBM_FP16_STORE ? 2 : 4); }
 size_t real_size(int prec) { return prec == PF_LBM_FP64 ? 8 : 4; }
 
-Layout make_layout(long long Np, int nb, int prec, int box_grid, int force_grid) {
+Layout make_layout(long long Np, int nb, int prec, int cpart_n, int force_grid) {
     const size_t rs = real_size(prec), ps = pop_size(prec);
     Layout L{};
     size_t off = 0;
@@ -103,7 +104,7 @@ Layout make_layout(long long Np, int nb, int prec, int box_grid, int force_grid)
     L.state = take(sizeof(StepState));
     L.sigma = take(sizeof(double) * (nb + 1) * (nb + 1));
     L.pforce = take(sizeof(double) * force_grid * std::max(nb, 1) * 6);
-    L.cpart = take(sizeof(ClassifyPart) * box_grid);
+    L.cpart = take(sizeof(ClassifyPart) * cpart_n);
     L.evlist = take(sizeof(uint32_t) * EV_CAP);
     L.total = off;
     return L;
@@ -296,13 +297,14 @@ int enqueue_step(pf_lbm *h) {
     k_psi<S><<<gd, b, 0, s>>>(p, fc, mask, cur, psi_prev, psi);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
     k_collide_stream<S><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, h->cfg.nz), dim3(64, 4), 0, s>>>(
-        p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->box_grid);
+        p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->cgrid);
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
         const dim3 gb(h->box_grid);
         k_body_forces<S><<<dim3(fbk), dim3(64 * force_waves<T>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev, mask, cur,
                                                                             pforce);
+        // one kernel per sweep; the phase fields end in buffer A every step
         k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB);
         k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA);
         k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB);
@@ -349,7 +351,7 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
     // solid / owner bits and the classification partials that the first step publishes
     if (h->nb > 0) {
         ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
-        k_classify_init<T><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, (const BodyDev *)(h->ws + h->L.bodies), phiA,
+        k_classify_init<T><<<dim3(h->cgrid), b, 0, s>>>(p, 0, st, (const BodyDev *)(h->ws + h->L.bodies), phiA,
                                                              mask, cpart);
     }
     HIPCHK(h, hipMemcpyAsync(tmp, rho0, sizeof(double) * h->N, hipMemcpyHostToDevice, s));
@@ -456,7 +458,8 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     // loops cover larger boxes), at most 4096 blocks
     const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
     const int box_grid = std::min(box_blocks, 2048), force_grid = std::min((box_blocks + 3) / 4, 256);
-    const Layout L = make_layout(Np, n_bodies, cfg->precision, box_grid, force_grid);
+    const int cgrid = box_grid;
+    const Layout L = make_layout(Np, n_bodies, cfg->precision, std::max(cgrid, box_grid), force_grid);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
     if (!workspace) return PF_LBM_OK;
     if (!out) return fail(nullptr, PF_LBM_EINVAL, "out is NULL");
@@ -479,6 +482,7 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     h->box_blocks = box_blocks;
     h->box_grid = box_grid;
     h->force_grid = force_grid;
+    h->cgrid = cgrid;
     const int np1 = n_bodies + 1;
     h->sigma.assign((size_t)np1 * np1, 0.0);
     for (int a = 0; a < np1; ++a)

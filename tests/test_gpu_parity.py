@@ -165,3 +165,30 @@ def test_graph_replay_matches_eager_launches(torch_cuda):
         assert np.array_equal(g.phi(), e.phi())
         assert np.array_equal(g.bodies()["F"], e.bodies()["F"])
     e.timing(False)
+
+
+@pytest.mark.parametrize("nb", [3, 5])
+def test_several_bodies_fp64(oracle_mod, torch_cuda, nb):
+    """Three bodies (the tiled phase update with 8x8x4 tiles) and five (one kernel per sweep):
+    moving, rotating spheres in a drop-filled ragged box, FP64 at round-off after 40 steps."""
+    from pflbm_inputs import coexistence_densities, default_params, liquid_density, sphere_phi
+    from pflbm_inputs.geometry import grid, mimg
+    from pflbm_inputs.workloads import Workload
+    shape = (22, 20, 26)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(11 + nb)
+    phis, bodies = [], []
+    for a in range(nb):
+        c = (4 + 18 * rng.random(), 3 + 14 * rng.random(), 3 + 16 * rng.random())
+        phis.append(sphere_phi(shape, c, 2.6 + rng.random(), 3.0))
+        bodies.append(dict(mass_density=3.0, wetting_rho=1.0, v=list(0.02 * rng.standard_normal(3)),
+                           w=list(0.005 * rng.standard_normal(3)), fixed=0))
+    phi = np.stack(phis)
+    s = phi.sum(0)
+    phi = np.where(s > 1, phi / np.where(s > 1, s, 1), phi)
+    rv, rl = coexistence_densities()
+    x, y, z = grid(shape)
+    d = np.sqrt(mimg(x - 13, nx) ** 2 + mimg(y - 10, ny) ** 2 + mimg(z - 11, nz) ** 2) - 7.0
+    w = Workload("bodies", default_params(nx, ny, nz, nb, e0=0.5), bodies, liquid_density(d, rl, rv, 3.0), phi)
+    sim, ref = _pair(oracle_mod, w, 40, "fp64")
+    _compare(sim, ref, 1e-11, 1e-9)
