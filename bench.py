@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -106,6 +108,51 @@ def cpu_baseline(w, seconds: float) -> dict:
                       f"after 1 warm-up step ({dt:.1f} s)"}
 
 
+def batched_sweep(args) -> int:
+    """The sweep of uneven two-sphere bridges (grids 48^3..128^3, seeded): every instance stepped
+    alone, one after the other, against all instances stepped together by pf_lbm_step_batch.
+    Prints one JSON line with both throughputs (MLUPS over all instances' nodes)."""
+    import torch
+
+    from paper_1902_10432_amd.simulation import Simulation, step_batch
+    from pflbm_inputs import bridge_sweep
+
+    t0 = time.perf_counter()
+    ws = bridge_sweep(args.batched, seed=0)
+    cells = sum(w.cells for w in ws)
+    log(f"{len(ws)} instances, {cells / 1e6:.1f} M nodes, generated in {time.perf_counter() - t0:.1f} s")
+    sims = [Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=args.precision) for w in ws]
+    tuned = None
+    if args.autotune:
+        tuned = [s.autotune(4) for s in sims]
+    step_batch(sims, args.warmup)
+    torch.cuda.synchronize()
+    # sequential: one instance at a time
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    seq_ms = 0.0
+    for s in sims:
+        ev[0].record(s.stream)
+        s.step(args.steps)
+        ev[1].record(s.stream)
+        torch.cuda.synchronize()
+        seq_ms += ev[0].elapsed_time(ev[1])
+    # batched
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_batch(sims, args.steps)
+    torch.cuda.synchronize()
+    bat_ms = (time.perf_counter() - t1) * 1e3
+    seq = cells * args.steps / (seq_ms / 1e3) / 1e6
+    bat = cells * args.steps / (bat_ms / 1e3) / 1e6
+    ok = all(np.isfinite(s.force_history(args.steps)).all() for s in sims)
+    out = {"metric": "batched uneven bridge sweep MLUPS", "value": round(bat, 2), "unit": "MLUPS",
+           "sequential": round(seq, 2), "vs_sequential": round(bat / seq, 3), "instances": len(ws),
+           "cells": cells, "steps": args.steps, "warmup": args.warmup, "precision": args.precision,
+           "autotuned": tuned is not None, "finite_force_histories": bool(ok), "data": "synthetic"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,9 +166,14 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16-storage comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
+    ap.add_argument("--batched", type=int, default=0, metavar="N",
+                    help="only the batched sweep of N uneven two-sphere instances against sequential runs")
+    ap.add_argument("--autotune", action="store_true", help="autotune each instance of the batched sweep")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 5)
+    if args.batched:
+        return batched_sweep(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)

@@ -160,6 +160,27 @@ int pf_lbm_diagnostics(pf_lbm *h, double *out4);
  * step time (ms), and 0 (reserved). */
 int pf_lbm_timing(pf_lbm *h, int32_t enable, double *out4);
 
+/* Per-body force and torque history of the last min(steps taken, max_steps, 8192) steps, oldest
+ * first, into a HOST array out[n][n_bodies][6] (F x, y, z, then T x, y, z, FP64; the values
+ * pf_lbm_forces reports after each of those steps); *n_out receives n.  The device keeps a ring
+ * of 8192 steps written inside the step, so a long run needs no host synchronisation per step
+ * (the batched sweeps record force histories this way).  Synchronises the handle's stream. */
+int pf_lbm_force_history(pf_lbm *h, int32_t max_steps, double *out, int32_t *n_out);
+
+/* Batched stepping of independent simulations (grids of any size): advances each of the n
+ * handles by n_steps, launching step pairs round robin over the handles.  Each handle launches
+ * on its own stream (given at pf_lbm_init), so the kernels of different instances overlap on the
+ * GPU; per instance the result is bit for bit that of pf_lbm_step.  Handles must be distinct.
+ * Returns the first error (its message on that handle). */
+int pf_lbm_step_batch(pf_lbm *const *handles, int32_t n, int32_t n_steps);
+
+/* Autotuner of the launch shapes that leave the arithmetic unchanged: the rows of the collide
+ * block (64 x 1, 2 or 4 threads) and the block size of the pseudopotential kernel (128 or 256).
+ * Each candidate runs 1 + steps_per_candidate steps of the simulation itself (the state
+ * advances), timed with HIP events; the fastest is kept.  out3 (HOST, may be NULL): chosen rows,
+ * chosen block size, its mean step time in ms. */
+int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3);
+
 /* Release the handle (the workspace stays the caller's).  NULL is ignored. */
 void pf_lbm_destroy(pf_lbm *h);
 

@@ -40,7 +40,8 @@ PF_LBM_DST_F64 = 0
 PF_LBM_DST_F32 = 1
 
 EXPORTED = ("pf_lbm_init", "pf_lbm_step", "pf_lbm_forces", "pf_lbm_fields", "pf_lbm_diagnostics",
-            "pf_lbm_timing", "pf_lbm_destroy", "pf_lbm_last_error")
+            "pf_lbm_timing", "pf_lbm_force_history", "pf_lbm_step_batch", "pf_lbm_autotune", "pf_lbm_destroy",
+            "pf_lbm_last_error")
 
 
 class PfLbmConfig(C.Structure):
@@ -96,6 +97,12 @@ def load_library():
     lib.pf_lbm_diagnostics.argtypes = [C.c_void_p, dp]
     lib.pf_lbm_timing.restype = C.c_int
     lib.pf_lbm_timing.argtypes = [C.c_void_p, C.c_int32, dp]
+    lib.pf_lbm_force_history.restype = C.c_int
+    lib.pf_lbm_force_history.argtypes = [C.c_void_p, C.c_int32, dp, C.POINTER(C.c_int32)]
+    lib.pf_lbm_step_batch.restype = C.c_int
+    lib.pf_lbm_step_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_int32]
+    lib.pf_lbm_autotune.restype = C.c_int
+    lib.pf_lbm_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
     lib.pf_lbm_destroy.restype = None
     lib.pf_lbm_destroy.argtypes = [C.c_void_p]
     lib.pf_lbm_last_error.restype = C.c_char_p
@@ -148,6 +155,25 @@ def pf_lbm_timing(h, enable: int):
     """enable=1 starts event timing; enable=0 stops it and returns (status, out[4])."""
     out = np.zeros(4)
     rc = load_library().pf_lbm_timing(h, int(enable), _dptr(out) if not enable else None)
+    return rc, out
+
+
+def pf_lbm_force_history(h, max_steps: int, n_bodies: int):
+    """(status, array [n, n_bodies, 6]) of the last n <= max_steps steps."""
+    out = np.zeros(max(max_steps, 1) * max(n_bodies, 1) * 6)
+    n = C.c_int32(0)
+    rc = load_library().pf_lbm_force_history(h, int(max_steps), _dptr(out), C.byref(n))
+    return rc, out[: n.value * n_bodies * 6].reshape(n.value, n_bodies, 6)
+
+
+def pf_lbm_step_batch(handles, n_steps: int) -> int:
+    arr = (C.c_void_p * max(len(handles), 1))(*handles)
+    return load_library().pf_lbm_step_batch(arr, len(handles), int(n_steps))
+
+
+def pf_lbm_autotune(h, steps_per_candidate: int):
+    out = np.zeros(3)
+    rc = load_library().pf_lbm_autotune(h, int(steps_per_candidate), _dptr(out))
     return rc, out
 
 

@@ -74,6 +74,7 @@ struct StepState {
     int32_t box[2][6];            // lo x, lo y, lo z, hi x, hi y, hi z
     uint32_t err;                 // bit 0 non-finite body state, bit 1 advection CFL above 1
     uint32_t n_events;            // nodes that changed side in this step's reclassification
+    uint32_t step_no, pad;        // steps started (counted by the step-state publish)
     unsigned long long n_f2s, n_s2f, n_lost;
     float srad[PF_LBM_MAX_BODIES];  // largest distance of a solid node from its body's centre
 };
@@ -266,18 +267,20 @@ __device__ __forceinline__ int wrap2(int i, int n) {
     return i;
 }
 
-// Run by the 4 waves of one block at the start of a step: combine the per-block
-// reclassification results of the previous step in a fixed order and publish
+// Run by the waves of one block at the start of a step: combine the per-block reclassification
+// results of the previous step in a fixed order and publish
 //  * this step's box (wave 0): phase-field support + 3-cell margin, the whole axis once it would
-//    wrap onto itself, lower corner brought into [0, n) (so unwrapped coordinates stay below 2 n);
-//  * per body (wave 1 + b % 3): the solid radius (bounds the repulsion search) and the volume
+//    wrap onto itself, lower corner brought into [0, n) (so unwrapped coordinates stay below 2 n),
+//    and count the step;
+//  * per body (waves 1.., round robin; wave 0 alone in a one-wave block): the solid radius
+//    (bounds the repulsion search) and the volume
 //    driving term h_a = (4 eta / pi^2) (V_ref - sum phi_a) / #{floor < phi_a < 1} (Sec. 3.3; 0
 //    without interface nodes), into the body table;
 // and clear the event count for this step's reclassification.  Each lane sums its parts with four
 // independent accumulators, then a fixed xor-shuffle tree combines the lanes.
-__device__ __forceinline__ void publish_step_state(int wave, int parity, int nx, int ny, int nz, int nb, double eta,
-                                                   StepState *st, BodyDev *bodies, const ClassifyPart *cpart,
-                                                   int nblk) {
+__device__ __forceinline__ void publish_step_state(int wave, int nwaves, int parity, int nx, int ny, int nz, int nb,
+                                                   double eta, StepState *st, BodyDev *bodies,
+                                                   const ClassifyPart *cpart, int nblk) {
     const int lane = (int)(threadIdx.x & 63);
     if (wave == 0) {
         int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
@@ -307,11 +310,14 @@ __device__ __forceinline__ void publish_step_state(int wave, int parity, int nx,
                 st->box[parity][3 + d] = empty ? -1 : h;
             }
             st->n_events = 0u;
+            st->step_no += 1u;
         }
-        return;
+        if (nwaves > 1) return;
     }
     const double PI = 3.14159265358979323846;
-    for (int b = wave - 1; b < nb; b += 3) {
+    // bodies on waves 1.. (round robin), or on wave 0 when the block has a single wave
+    const int bw = nwaves > 1 ? wave - 1 : 0, bstride = nwaves > 1 ? nwaves - 1 : 1;
+    for (int b = bw; b < nb; b += bstride) {
         float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f, r3 = 0.0f;
         double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0;

@@ -14,7 +14,7 @@ __global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, const S *__restrict_
                                              const BodyDev *__restrict__ bodies, const ArT<S> *__restrict__ psi_ref,
                                              ArT<S> *__restrict__ psi) {
     using T = ArT<S>;
-    const int idx = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int idx = xcd_block(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
     if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed
     const cell_t m = mask[idx];
     T out;
@@ -97,15 +97,15 @@ __device__ __forceinline__ void wall_velocity(const Prm<T> &p, const BodyDev &B,
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// 3-D launch (64 x 4 threads per block, grid ceil(nx/64) x ceil(ny/4) x nz) with the flat block
-// id remapped so that each XCD works on a contiguous range of planes.
+// 3-D launch (64 x R threads per block, R = 1, 2 or 4, grid ceil(nx/64) x ceil(ny/R) x nz) with the
+// flat block id remapped so that each XCD works on a contiguous range of planes.
 __device__ __forceinline__ bool cell_of_block(int nx, int ny, int &x, int &y, int &z) {
     const int gx = gridDim.x, gy = gridDim.y;
     const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
     const int r = xcd_block(lin, gx * gy * gridDim.z);
     const int bz = r / (gx * gy), rem = r - bz * gx * gy, by = rem / gx, bxx = rem - by * gx;
     x = bxx * 64 + (int)threadIdx.x;
-    y = by * 4 + (int)threadIdx.y;
+    y = by * (int)blockDim.y + (int)threadIdx.y;
     z = bz;
     return x < nx && y < ny;
 }
@@ -134,7 +134,8 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
                                                         const ClassifyPart *__restrict__ cpart, int cblk) {
     using T = ArT<S>;
     if (cpart && (blockIdx.x | blockIdx.y | blockIdx.z) == 0)
-        publish_step_state((int)threadIdx.y, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart, cblk);
+        publish_step_state((int)threadIdx.y, (int)blockDim.y, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart,
+                           cblk);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     int x, y, z;
     if (!cell_of_block(nx, ny, x, y, z)) return;

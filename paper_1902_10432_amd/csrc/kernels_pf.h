@@ -53,10 +53,12 @@ __device__ __forceinline__ void block_totals(const double *part, int nblk, int K
 // same fixed order and advances the bodies from the current table with dt = 1: V += F/M,
 // X += V, omega += I^-1 T; block 0 publishes the result (with F, T) in the next table, which the
 // later kernels of the step read.
+// hist (first sweep): ring of hcap steps of per-body force and torque, [step][body][6]
 template <typename T, int AX>
 __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState *st, const BodyDev *__restrict__ cur,
                                                 BodyDev *__restrict__ next, const double *__restrict__ fpart, int fblk,
-                                                const double *__restrict__ src, double *__restrict__ dst) {
+                                                const double *__restrict__ src, double *__restrict__ dst,
+                                                double *__restrict__ hist, int hcap) {
     __shared__ double tot[PF_LBM_MAX_BODIES * 6];
     __shared__ double lb[PF_LBM_MAX_BODIES][9];  // X, V, W of each body for this sweep
     const int tid = threadIdx.x;
@@ -96,6 +98,13 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
                 }
                 next[tid] = Bn;
                 if (!finite) atomicOr(&st->err, 1u);
+                if (hist) {
+                    double *hrow = hist + ((long long)((st->step_no - 1u) % (uint32_t)hcap) * nbod + tid) * 6;
+                    for (int d = 0; d < 3; ++d) {
+                        hrow[d] = F[d];
+                        hrow[3 + d] = Tq[d];
+                    }
+                }
             }
         }
     } else {

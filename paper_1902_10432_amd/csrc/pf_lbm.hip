@@ -25,10 +25,12 @@ constexpr size_t ALIGN = 256;
 // capacity of the per-step list of nodes that changed side (beyond it the closing kernels scan
 // the whole box)
 constexpr uint32_t EV_CAP = 1u << 16;
+// steps of per-body force / torque history kept on the device (ring)
+constexpr int HIST_CAP = 8192;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t fA, fB, psi, psiB, phiA, phiB, mask, bodies, state, sigma, pforce, cpart, evlist, total;
+    size_t fA, fB, psi, psiB, phiA, phiB, mask, bodies, state, sigma, pforce, cpart, evlist, hist, total;
 };
 
 }  // namespace
@@ -44,6 +46,9 @@ struct pf_lbm {
     int dense_blocks = 0, box_blocks = 1;
     int box_grid = 1, force_grid = 1;  // grids of the box kernels and of the force scan
     int cgrid = 1;  // classification partials written per step (grid of the phase update)
+    // launch shapes that leave the arithmetic unchanged (pf_lbm_autotune): rows of the collide
+    // block (64 x rows threads) and the block size of the pseudopotential kernel
+    int rows = 4, psi_bs = 256;
     long long steps = 0;
     std::vector<double> sigma;
     std::string err;
@@ -106,6 +111,7 @@ Layout make_layout(long long Np, int nb, int prec, int cpart_n, int force_grid) 
     L.pforce = take(sizeof(double) * force_grid * std::max(nb, 1) * 6);
     L.cpart = take(sizeof(ClassifyPart) * cpart_n);
     L.evlist = take(sizeof(uint32_t) * EV_CAP);
+    L.hist = take(sizeof(double) * HIST_CAP * std::max(nb, 1) * 6);
     L.total = off;
     return L;
 }
@@ -279,7 +285,7 @@ int enqueue_step(pf_lbm *h) {
     const double *sigma = (const double *)(h->ws + h->L.sigma);
     double *pforce = (double *)(h->ws + h->L.pforce);
     ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
-    const dim3 gd(h->dense_blocks), b(256);
+    const dim3 gd((unsigned)((h->N + h->psi_bs - 1) / h->psi_bs)), b(256);
     hipStream_t s = h->stream;
     hipEvent_t *ev = nullptr;
     if (h->timing && h->timed < 4096) {
@@ -294,9 +300,10 @@ int enqueue_step(pf_lbm *h) {
         ++h->timed;
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
-    k_psi<S><<<gd, b, 0, s>>>(p, fc, mask, cur, psi_prev, psi);
+    k_psi<S><<<gd, dim3(h->psi_bs), 0, s>>>(p, fc, mask, cur, psi_prev, psi);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
-    k_collide_stream<S><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, h->cfg.nz), dim3(64, 4), 0, s>>>(
+    k_collide_stream<S><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + h->rows - 1) / h->rows, h->cfg.nz), dim3(64, h->rows),
+                          0, s>>>(
         p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->cgrid);
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
@@ -305,9 +312,10 @@ int enqueue_step(pf_lbm *h) {
         k_body_forces<S><<<dim3(fbk), dim3(64 * force_waves<T>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev, mask, cur,
                                                                             pforce);
         // one kernel per sweep; the phase fields end in buffer A every step
-        k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB);
-        k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA);
-        k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB);
+        k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB,
+                                        (double *)(h->ws + h->L.hist), HIST_CAP);
+        k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA, nullptr, 0);
+        k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB, nullptr, 0);
         uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
         launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
         const dim3 ge(std::min(h->box_grid, 256));
@@ -660,6 +668,93 @@ int pf_lbm_timing(pf_lbm *h, int32_t enable, double *out4) {
         out4[3] = 0.0;
     }
     h->timing = false;
+    return PF_LBM_OK;
+}
+
+int pf_lbm_force_history(pf_lbm *h, int32_t max_steps, double *out, int32_t *n_out) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    if (max_steps < 0 || (max_steps > 0 && !out)) return fail(h, PF_LBM_EINVAL, "bad output");
+    const long long avail = std::min<long long>(h->nb > 0 ? h->steps : 0, HIST_CAP);
+    const int n = (int)std::min<long long>(avail, max_steps);
+    if (n_out) *n_out = n;
+    if (n == 0) return PF_LBM_OK;
+    const size_t row = sizeof(double) * h->nb * 6;
+    std::vector<double> ring((size_t)HIST_CAP * h->nb * 6);
+    HIPCHK(h, hipMemcpyAsync(ring.data(), h->ws + h->L.hist, ring.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < n; ++k) {
+        const long long step = h->steps - n + k;  // 0-based index of the step
+        std::memcpy((char *)out + (size_t)k * row, (const char *)ring.data() + (size_t)(step % HIST_CAP) * row, row);
+    }
+    return PF_LBM_OK;
+}
+
+int pf_lbm_step_batch(pf_lbm *const *handles, int32_t n, int32_t n_steps) {
+    if (!handles || n < 0) return fail(nullptr, PF_LBM_EINVAL, "handles is NULL or n < 0");
+    if (n_steps < 0) return fail(nullptr, PF_LBM_EINVAL, "n_steps must be >= 0");
+    for (int i = 0; i < n; ++i)
+        if (!handles[i]) return fail(nullptr, PF_LBM_EINVAL, "handle %d is NULL", i);
+    // step pairs round robin over the instances: each handle launches on its own stream, so the
+    // launches of different instances queue side by side and their kernels overlap
+    for (int done = 0; done < n_steps; done += 2) {
+        const int chunk = std::min(2, n_steps - done);
+        for (int i = 0; i < n; ++i) {
+            const int rc = pf_lbm_step(handles[i], chunk);
+            if (rc != PF_LBM_OK) return rc;
+        }
+    }
+    return PF_LBM_OK;
+}
+
+int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    if (steps_per_candidate < 2) return fail(h, PF_LBM_EINVAL, "steps_per_candidate must be >= 2");
+    if (h->timing) return fail(h, PF_LBM_EINVAL, "autotune while timing is on");
+    const int rows_c[3] = {1, 2, 4}, bs_c[2] = {128, 256};
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    double best = 1e300;
+    int best_rows = h->rows, best_bs = h->psi_bs;
+    for (int r : rows_c)
+        for (int bs : bs_c) {
+            h->rows = r;
+            h->psi_bs = bs;
+            // one untimed step with the candidate, then the timed ones (launched one by one)
+            int rc = eager_step(h);
+            if (rc == PF_LBM_OK) {
+                HIPCHK(h, hipEventRecord(e0, h->stream));
+                for (int k = 0; k < steps_per_candidate && rc == PF_LBM_OK; ++k) rc = eager_step(h);
+                HIPCHK(h, hipEventRecord(e1, h->stream));
+            }
+            if (rc != PF_LBM_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc;
+            }
+            HIPCHK(h, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_rows = r;
+                best_bs = bs;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->rows = best_rows;
+    h->psi_bs = best_bs;
+    // the captured step pair used the old shapes: capture again on the next pf_lbm_step
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    h->graph_failed = false;
+    if (out3) {
+        out3[0] = best_rows;
+        out3[1] = best_bs;
+        out3[2] = best / steps_per_candidate;
+    }
     return PF_LBM_OK;
 }
 

@@ -126,7 +126,28 @@ class Simulation:
         self._check(rc)
         return {"steps": int(out[0]), "kernel_ms": out[1], "step_ms": out[2]}
 
+    def force_history(self, max_steps: int = 8192) -> np.ndarray:
+        """[n, n_bodies, 6] FP64 force (x, y, z) and torque of the last n steps, oldest first."""
+        rc, out = B.pf_lbm_force_history(self._h, max_steps, self.nb)
+        self._check(rc)
+        return out
+
+    def autotune(self, steps_per_candidate: int = 10) -> dict:
+        """Pick the fastest result-invariant launch shapes (advances the simulation)."""
+        rc, out = B.pf_lbm_autotune(self._h, steps_per_candidate)
+        self._check(rc)
+        return {"rows": int(out[0]), "psi_block": int(out[1]), "ms_per_step": out[2]}
+
     def diag(self) -> dict:
         rc, out = B.pf_lbm_diagnostics(self._h)
         self._check(rc)
         return {"step": int(out[0]), "n_f2s": int(out[1]), "n_s2f": int(out[2]), "n_lost": int(out[3])}
+
+
+def step_batch(sims, n_steps: int) -> None:
+    """Advance independent simulations (each on its own stream) together: their launches
+    interleave so that the kernels of different instances overlap on the GPU."""
+    rc = B.pf_lbm_step_batch([s._h for s in sims], n_steps)
+    if rc != B.PF_LBM_OK:
+        errs = [B.pf_lbm_last_error(s._h) for s in sims]
+        raise PfLbmError(rc, "; ".join(e for e in errs if e) or B.pf_lbm_last_error(None))

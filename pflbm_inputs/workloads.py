@@ -189,6 +189,78 @@ def two_spheres_bridge(n: int = 128, radius: float = 20.0, gap: float = 4.0, liq
     return Workload("two_spheres_bridge", p, bodies, rho, phis, meta)
 
 
+def bridge_pair(shape, r1: float, r2: float, gap: float, liquid_fraction: float, theta_deg: float,
+                width: float = 4.0, **over) -> Workload:
+    """Two spheres of radii r1, r2 on the x axis with a surface gap, joined by a tanh-smoothed
+    cylindrical bridge of liquid volume V_L = c V_S / (1 - c), c the liquid fraction
+    V_L / (V_L + V_S) of Sec. 2.2 and V_S the two spheres' volume; the bridge radius is found by
+    bisection (capped at the smaller radius)."""
+    nz, ny, nx = shape
+    rv, rl = coexistence_densities()
+    cy, cz = ny / 2.0, nz / 2.0
+    c1 = (nx / 2.0 - gap / 2.0 - r1, cy, cz)
+    c2 = (nx / 2.0 + gap / 2.0 + r2, cy, cz)
+    phis = np.stack([sphere_phi(shape, c1, r1, width), sphere_phi(shape, c2, r2, width)])
+    tot = phis.sum(0)
+    phis = np.where(tot > 1.0, phis / np.where(tot > 1.0, tot, 1.0), phis)
+    solid = _solid_mask(phis)
+    # the bridge lives in a window around the segment between the centres
+    m = int(math.ceil(2 * width)) + 1
+    x0, x1 = max(int(c1[0]) - m, 0), min(int(math.ceil(c2[0])) + m + 1, nx)
+    rr = int(math.ceil(min(r1, r2))) + m
+    y0, y1 = max(int(cy) - rr, 0), min(int(cy) + rr + 1, ny)
+    z0, z1 = max(int(cz) - rr, 0), min(int(cz) + rr + 1, nz)
+    x, y, z = grid(shape)
+    win = (slice(z0, z1), slice(y0, y1), slice(x0, x1))
+    xm = 0.5 * (c1[0] + c2[0])
+    half = 0.5 * (c2[0] - c1[0])
+    rperp_w = np.sqrt((y[win] - cy) ** 2 + (z[win] - cz) ** 2)
+    dx_w = np.abs(x[win] - xm) - half
+    solid_w = solid[win]
+    target = liquid_fraction / (1.0 - liquid_fraction) * 4.0 / 3.0 * math.pi * (r1 ** 3 + r2 ** 3)
+
+    def vol(rb):
+        return _liquid_volume(liquid_density(np.maximum(rperp_w - rb, dx_w), rl, rv, width), solid_w, rv, rl)
+
+    rmax = min(r1, r2)
+    rb = rmax if vol(rmax) < target else _bisect(vol, 0.5, rmax, target, iters=30)
+    rperp = np.sqrt((y - cy) ** 2 + (z - cz) ** 2)
+    rho = liquid_density(np.maximum(rperp - rb, np.abs(x - xm) - half), rl, rv, width)
+    wet = wetting_rho_for_angle(theta_deg)
+    bodies = [_body(SPHERE_DENSITY, wet), _body(SPHERE_DENSITY, wet)]
+    p = default_params(nx, ny, nz, 2, **over)
+    meta = {"radii": (r1, r2), "gap": gap, "liquid_fraction": liquid_fraction, "theta_deg": theta_deg,
+            "bridge_radius": rb, "liquid_volume": vol(rb), "target_volume": target, "centres": (c1, c2),
+            "rho_l": rl, "rho_v": rv}
+    return Workload("bridge_pair", p, bodies, rho, phis, meta)
+
+
+def bridge_sweep_params(n: int = 64, seed: int = 0, min_len: int = 48, max_len: int = 128):
+    """Seeded parameters of a sweep of uneven two-sphere bridges (PCG64): radii U[8, 30], surface gap
+    U[2, 8], liquid fraction U[0.01, 0.20], contact angle U[0, 60] degrees; box length per axis
+    U[min_len, max_len] rounded up to a multiple of 8, redrawn until the pair fits with 8 cells
+    to spare on every side (x: 2 r1 + 2 r2 + gap + 16; y, z: 2 max(r) + 16)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    while len(out) < n:
+        r1, r2 = rng.uniform(8.0, 30.0, 2)
+        gap = rng.uniform(2.0, 8.0)
+        c = rng.uniform(0.01, 0.20)
+        theta = rng.uniform(0.0, 60.0)
+        L = [int(math.ceil(v / 8.0) * 8) for v in rng.uniform(min_len, max_len, 3)]
+        if L[0] < 2 * (r1 + r2) + gap + 16 or min(L[1], L[2]) < 2 * max(r1, r2) + 16 or max(L) > max_len:
+            continue
+        out.append({"shape": (L[2], L[1], L[0]), "r1": float(r1), "r2": float(r2), "gap": float(gap),
+                    "liquid_fraction": float(c), "theta_deg": float(theta)})
+    return out
+
+
+def bridge_sweep(n: int = 64, seed: int = 0, **over) -> list:
+    """The sweep of bridge_sweep_params as workloads."""
+    return [bridge_pair(q["shape"], q["r1"], q["r2"], q["gap"], q["liquid_fraction"], q["theta_deg"], **over)
+            for q in bridge_sweep_params(n, seed)]
+
+
 def tetrahedron_drop(n: int = 256, radius: float = 24.0, gap: float = 4.0, liquid_fraction: float = 0.05,
                      theta_deg: float = 30.0, width: float = 4.0, seed: int = 0, amplitude: float = 1e-3,
                      **over) -> Workload:
