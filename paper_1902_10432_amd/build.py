@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "pf_lbm.hip")
+SRCS = [os.path.join(HERE, "csrc", "pf_lbm.hip"), os.path.join(HERE, "csrc", "mlp.hip")]
 LIB = os.path.join(HERE, "libpflbm.so")
 ARCH = os.environ.get("PFLBM_OFFLOAD_ARCH", "gfx950")
 
@@ -23,11 +23,11 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source of the library; always rebuilds."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, SRC, "-o", tmp]
+    cmd = [hipcc, *HIPCC_FLAGS, *SRCS, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building " + SRC)
+        raise RuntimeError("hipcc failed building " + " ".join(SRCS))
     if verbose:
         sys.stderr.write(res.stderr)
     os.replace(tmp, LIB)

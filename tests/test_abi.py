@@ -111,3 +111,32 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(binding.LibraryMissing):
         binding.load_library()
+
+
+def test_mlp_header_symbols_exported(B):
+    from paper_1902_10432_amd import surrogate
+    hdr = open(os.path.join(ROOT, "include", "pf_mlp.h")).read()
+    declared = set(re.findall(r"\b(pf_mlp_[a-z_]+)\s*\(", hdr))
+    lib = C.CDLL(B.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(surrogate.MLP_EXPORTED)
+
+
+@pytest.mark.parametrize("field,value", [("n_in", 0), ("n_in", 17), ("hidden", 24), ("hidden", 528),
+                                         ("layers", 0), ("layers", 9), ("max_batch", 0), ("max_batch", 65537)])
+def test_mlp_invalid_configs_rejected(B, field, value):
+    from paper_1902_10432_amd import surrogate as S
+    lib = S._load()
+    cfg = S.PfMlpConfig(C.sizeof(S.PfMlpConfig), 4, 128, 4, 1024)
+    need = C.c_size_t(0)
+    h = C.c_void_p()
+    assert lib.pf_mlp_init(C.byref(cfg), 0, None, 0, None, C.byref(h), C.byref(need)) == B.PF_LBM_OK
+    # parameters + gradients + two Adam moments in FP32 and two BF16 weight copies
+    n_par = 4 * 128 + 128 + 3 * (128 * 128 + 128) + 128 + 1
+    n_w = 4 * 128 + 3 * 128 * 128 + 128
+    assert need.value >= 16 * n_par + 4 * n_w + 1024 * 128 * (4 + 2) * 4
+    setattr(cfg, field, value)
+    rc = lib.pf_mlp_init(C.byref(cfg), 0, None, 0, None, C.byref(h), C.byref(need))
+    assert rc == B.PF_LBM_EINVAL
+    assert lib.pf_mlp_last_error(None)
