@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", "pf_lbm.hip"), os.path.join(HERE, "csrc", "mlp.hip")]
+SRCS = [os.path.join(HERE, "csrc", n) for n in ("pf_lbm.hip", "mlp.hip", "dem.hip")]
 LIB = os.path.join(HERE, "libpflbm.so")
 ARCH = os.environ.get("PFLBM_OFFLOAD_ARCH", "gfx950")
 

@@ -278,6 +278,13 @@ int upload_params(pf_mlp *h, const float *params) {
 
 }  // namespace
 
+__attribute__((visibility("hidden"))) void pfm_internal_info(const pf_mlp *h, int *n_in, int *max_batch,
+                                                             void **stream) {
+    *n_in = h ? h->cfg.n_in : 0;
+    *max_batch = h ? h->cfg.max_batch : 0;
+    *stream = h ? (void *)h->stream : nullptr;
+}
+
 extern "C" {
 
 int pf_mlp_init(const pf_mlp_config *cfg, uint64_t seed, void *workspace, size_t ws_bytes, void *hip_stream,

@@ -122,3 +122,125 @@ class Surrogate:
         if h:
             _load().pf_mlp_destroy(h)
             self._h = None
+
+
+DEM_EXPORTED = ("pf_dem_init", "pf_dem_evaluate", "pf_dem_step", "pf_dem_state", "pf_dem_pairs",
+                "pf_dem_set_overrides", "pf_dem_destroy", "pf_dem_last_error")
+
+
+class PfDemConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n", C.c_int32), ("max_neighbours", C.c_int32),
+                ("max_pairs", C.c_int32), ("box", C.c_double), ("dt", C.c_double), ("density", C.c_double),
+                ("k_n", C.c_double), ("gamma_n", C.c_double), ("theta", C.c_double),
+                ("liquid_fraction", C.c_double), ("gap_min", C.c_double), ("gap_max", C.c_double),
+                ("in_shift", C.c_float * 4), ("in_scale", C.c_float * 4), ("out_shift", C.c_float),
+                ("out_scale", C.c_float)]
+
+
+def _load_dem():
+    lib = _load()
+    if not getattr(lib, "_dem_ready", False):
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        lib.pf_dem_init.restype = C.c_int
+        lib.pf_dem_init.argtypes = [C.POINTER(PfDemConfig), dp, dp, dp, vp, vp, C.c_size_t, vp, C.POINTER(vp),
+                                    C.POINTER(C.c_size_t)]
+        lib.pf_dem_evaluate.restype = C.c_int
+        lib.pf_dem_evaluate.argtypes = [vp]
+        lib.pf_dem_step.restype = C.c_int
+        lib.pf_dem_step.argtypes = [vp, C.c_int32]
+        lib.pf_dem_state.restype = C.c_int
+        lib.pf_dem_state.argtypes = [vp, dp, dp, dp]
+        lib.pf_dem_pairs.restype = C.c_int
+        lib.pf_dem_pairs.argtypes = [vp, C.c_int32, ip, dp, dp, ip]
+        lib.pf_dem_set_overrides.restype = C.c_int
+        lib.pf_dem_set_overrides.argtypes = [vp, C.c_int32, ip, dp]
+        lib.pf_dem_destroy.restype = None
+        lib.pf_dem_destroy.argtypes = [vp]
+        lib.pf_dem_last_error.restype = C.c_char_p
+        lib.pf_dem_last_error.argtypes = [vp]
+        lib._dem_ready = True
+    return lib
+
+
+def dem_config(n, box, dt, density, k_n, gamma_n, theta, liquid_fraction, gap_min, gap_max, norm,
+               max_neighbours=32, max_pairs=8192) -> PfDemConfig:
+    """norm: dict with in_shift[4], in_scale[4], out_shift, out_scale (network normalisation)."""
+    cfg = PfDemConfig()
+    cfg.struct_size = C.sizeof(PfDemConfig)
+    cfg.n, cfg.max_neighbours, cfg.max_pairs = int(n), int(max_neighbours), int(max_pairs)
+    cfg.box, cfg.dt, cfg.density, cfg.k_n, cfg.gamma_n = float(box), float(dt), float(density), float(k_n), float(gamma_n)
+    cfg.theta, cfg.liquid_fraction, cfg.gap_min, cfg.gap_max = float(theta), float(liquid_fraction), float(gap_min), float(gap_max)
+    for k in range(4):
+        cfg.in_shift[k] = float(norm["in_shift"][k])
+        cfg.in_scale[k] = float(norm["in_scale"][k])
+    cfg.out_shift, cfg.out_scale = float(norm["out_shift"]), float(norm["out_scale"])
+    return cfg
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class SphereRun:
+    """Many-sphere rigid-body run with surrogate bridge forces (pf_dem.h) on the network's stream."""
+
+    def __init__(self, net: Surrogate, cfg: PfDemConfig, radii, x0, v0):
+        lib = _load_dem()
+        self.net, self.n = net, cfg.n
+        self.max_pairs = cfg.max_pairs
+        R = np.ascontiguousarray(radii, dtype=np.float64)
+        x = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1)
+        v = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1)
+        assert R.size == cfg.n and x.size == 3 * cfg.n and v.size == 3 * cfg.n
+        need = C.c_size_t(0)
+        h = C.c_void_p()
+        strm = C.c_void_p(net.stream.cuda_stream)
+        self._chk0(lib.pf_dem_init(C.byref(cfg), _dptr(R), _dptr(x), _dptr(v), net._h, None, 0, strm, C.byref(h),
+                                   C.byref(need)))
+        self.workspace = torch.empty(need.value, dtype=torch.uint8, device=net.device)
+        torch.cuda.synchronize(net.device)
+        self._chk0(lib.pf_dem_init(C.byref(cfg), _dptr(R), _dptr(x), _dptr(v), net._h,
+                                   C.c_void_p(self.workspace.data_ptr()), need.value, strm, C.byref(h), C.byref(need)))
+        self._h = h
+
+    @staticmethod
+    def _chk0(rc):
+        if rc != B.PF_LBM_OK:
+            raise SurrogateError(f"pf_dem_init {rc}: {_load_dem().pf_dem_last_error(None).decode()}")
+
+    def _chk(self, rc):
+        if rc != B.PF_LBM_OK:
+            raise SurrogateError(f"pf_dem {rc}: {_load_dem().pf_dem_last_error(self._h).decode()}")
+
+    def evaluate(self):
+        self._chk(_load_dem().pf_dem_evaluate(self._h))
+
+    def step(self, n=1):
+        self._chk(_load_dem().pf_dem_step(self._h, int(n)))
+
+    def state(self):
+        x, v, f = (np.empty((self.n, 3)) for _ in range(3))
+        self._chk(_load_dem().pf_dem_state(self._h, _dptr(x), _dptr(v), _dptr(f)))
+        return {"x": x, "v": v, "F": f}
+
+    def pairs(self):
+        cnt = C.c_int32(0)
+        ij = np.empty((self.max_pairs, 2), dtype=np.int32)
+        feat = np.empty((self.max_pairs, 4))
+        force = np.empty(self.max_pairs)
+        self._chk(_load_dem().pf_dem_pairs(self._h, self.max_pairs, ij.ctypes.data_as(C.POINTER(C.c_int32)),
+                                           _dptr(feat), _dptr(force), C.byref(cnt)))
+        k = min(cnt.value, self.max_pairs)
+        return {"ij": ij[:k].copy(), "features": feat[:k].copy(), "force": force[:k].copy()}
+
+    def set_overrides(self, ij, force):
+        ij = np.ascontiguousarray(ij, dtype=np.int32).reshape(-1, 2)
+        force = np.ascontiguousarray(force, dtype=np.float64).reshape(-1)
+        self._chk(_load_dem().pf_dem_set_overrides(self._h, len(force), ij.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                   _dptr(force)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load_dem().pf_dem_destroy(h)
+            self._h = None

@@ -12,6 +12,6 @@ from .geometry import (  # noqa: F401
 )
 from .coexistence import coexistence_densities  # noqa: F401
 from .workloads import (  # noqa: F401
-    Workload, planar_bridge, plates_bridge, two_spheres_bridge, bridge_pair, bridge_sweep, bridge_sweep_params, tetrahedron_drop, tiny_moving_body, uniform_fluid,
+    Workload, planar_bridge, plates_bridge, two_spheres_bridge, bridge_pair, bridge_sweep, bridge_sweep_params, tetrahedron_drop, tiny_moving_body, uniform_fluid, BRIDGE_VAPOUR,
     WORKLOADS, make_workload,
 )

@@ -14,10 +14,11 @@ SNAP = 1e-2
 
 
 def grid(shape):
+    """Cell-centre coordinates x, y, z as read-only full-shape broadcast views."""
     nz, ny, nx = shape
-    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
-                          np.arange(nx, dtype=np.float64), indexing="ij")
-    return x, y, z
+    return (np.broadcast_to(np.arange(nx, dtype=np.float64)[None, None, :], shape),
+            np.broadcast_to(np.arange(ny, dtype=np.float64)[None, :, None], shape),
+            np.broadcast_to(np.arange(nz, dtype=np.float64)[:, None, None], shape))
 
 
 def mimg(d, L):
@@ -49,9 +50,12 @@ def box_signed_distance(shape, lo, hi):
 
 
 def sphere_signed_distance(shape, centre, radius):
-    x, y, z = grid(shape)
     nz, ny, nx = shape
-    r = np.sqrt(mimg(x - centre[0], nx) ** 2 + mimg(y - centre[1], ny) ** 2 + mimg(z - centre[2], nz) ** 2)
+    # per-axis minimum images, summed x + y + z in that order
+    dx = mimg(np.arange(nx, dtype=np.float64) - centre[0], nx) ** 2
+    dy = mimg(np.arange(ny, dtype=np.float64) - centre[1], ny) ** 2
+    dz = mimg(np.arange(nz, dtype=np.float64) - centre[2], nz) ** 2
+    r = np.sqrt((dx[None, None, :] + dy[None, :, None]) + dz[:, None, None])
     return r - radius
 
 

@@ -140,3 +140,34 @@ def test_mlp_invalid_configs_rejected(B, field, value):
     rc = lib.pf_mlp_init(C.byref(cfg), 0, None, 0, None, C.byref(h), C.byref(need))
     assert rc == B.PF_LBM_EINVAL
     assert lib.pf_mlp_last_error(None)
+
+
+def test_dem_header_symbols_exported(B):
+    from paper_1902_10432_amd import surrogate
+    hdr = open(os.path.join(ROOT, "include", "pf_dem.h")).read()
+    declared = set(re.findall(r"\b(pf_dem_[a-z_]+)\s*\(", hdr))
+    lib = C.CDLL(B.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(surrogate.DEM_EXPORTED)
+
+
+_NORM = {"in_shift": [0.0] * 4, "in_scale": [1.0] * 4, "out_shift": 0.0, "out_scale": 1.0}
+
+
+@pytest.mark.parametrize("field,value", [("n", 1), ("n", 16385), ("max_neighbours", 0), ("max_neighbours", 65),
+                                         ("max_pairs", 0), ("dt", 0.0), ("density", -1.0), ("k_n", -1.0),
+                                         ("theta", 2.0), ("liquid_fraction", 1.0), ("gap_min", -0.1),
+                                         ("gap_max", 0.0)])
+def test_dem_invalid_configs_rejected(B, field, value):
+    from paper_1902_10432_amd import surrogate as S
+    lib = S._load_dem()
+    cfg = S.dem_config(100, 50.0, 1.0, 1.0, 1.0, 0.1, 0.5, 0.1, 0.0, 2.0, _NORM)
+    need = C.c_size_t(0)
+    h = C.c_void_p()
+    assert lib.pf_dem_init(C.byref(cfg), None, None, None, None, None, 0, None, C.byref(h), C.byref(need)) == 0
+    assert need.value >= 100 * (8 + 3 * 24 + 4 * 32) + 8192 * (8 + 32 + 8 + 16 + 4)
+    setattr(cfg, field, value)
+    rc = lib.pf_dem_init(C.byref(cfg), None, None, None, None, None, 0, None, C.byref(h), C.byref(need))
+    assert rc == B.PF_LBM_EINVAL
+    assert lib.pf_dem_last_error(None)
