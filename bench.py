@@ -153,6 +153,68 @@ def batched_sweep(args) -> int:
     return 0
 
 
+def mlp_forward_rate(batch: int = 65536, reps: int = 50) -> dict:
+    """Forward throughput of the 4 -> 128 x 4 -> 1 network on one batch, timed with HIP events on
+    the network's stream."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1902_10432_amd import surrogate as S
+
+    net = S.Surrogate(4, 128, 4, max_batch=batch, seed=0)
+    x = torch.randn(batch, 4, device="cuda")
+    y = torch.empty(batch, device="cuda")
+    lib = S._load()
+    torch.cuda.synchronize()
+    for _ in range(5):
+        lib.pf_mlp_forward(net._h, C.c_void_p(x.data_ptr()), batch, C.c_void_p(y.data_ptr()))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(net.stream)
+    for _ in range(reps):
+        lib.pf_mlp_forward(net._h, C.c_void_p(x.data_ptr()), batch, C.c_void_p(y.data_ptr()))
+    ev[1].record(net.stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    flops = 2.0 * batch * (4 * 128 + 3 * 128 * 128 + 128)
+    return {"batch": batch, "ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 2),
+            "rows_per_s": round(batch / ms * 1e3, 1)}
+
+
+def surrogate_run(args) -> int:
+    """The learned bridge-force surrogate end to end: training data from the two-sphere bridge
+    sweep (64 bridges per seed, fixed spheres, 2000 steps), training on the GPU, and the
+    1000-sphere rigid-body run at 3 % liquid in which 32 bridges are re-solved at 96^3 every 100
+    steps as error judge and fallback.  Prints one JSON line: the cost ratio per bridge force
+    (field solve / network), the network's error on the judged bridges, and the network's forward
+    throughput."""
+    from paper_1902_10432_amd import deploy as Dp
+
+    t0 = time.perf_counter()
+    X, y, st = Dp.training_set(64, seeds=tuple(range(args.surrogate_seeds)), log=log)
+    t_data = time.perf_counter() - t0
+    norm = Dp.normalisation(X, y)
+    net, rep = Dp.train(X, y, norm, log=log)
+    s = Dp.deploy(net, norm, steps=args.surrogate_steps, log=log)
+    fwd = mlp_forward_rate()
+    rounds = s.pop("rounds")
+    out = {"metric": "surrogate bridge force: GPU time per bridge, PF-LBM re-solve / network",
+           "value": round(s["speedup_per_bridge"], 1), "unit": "x", "higher_is_better": True,
+           "judged_rmse": round(s["rmse"], 5), "judged_field_rms": round(s["rms_field"], 5),
+           "judged_rel_rmse": round(s["rmse"] / s["rms_field"], 4), "judged": s["judged"], "fallbacks": s["fallbacks"],
+           "seconds_per_bridge_network": s["seconds_per_bridge_network"],
+           "seconds_per_bridge_field": s["seconds_per_bridge_field"],
+           "training": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in rep.items()},
+           "training_data_seconds": round(t_data, 1), "training_bridges": int(len(y)),
+           "run": {k: v for k, v in s.items() if k not in ("seconds_per_bridge_network", "seconds_per_bridge_field")},
+           "bridges_per_round": [r.get("bridges") for r in rounds], "network_forward": fwd,
+           "dtype": "bf16-mfma/f32", "data": "synthetic",
+           "config": {"workload": "1000 spheres, radii 12..18, 3% liquid, theta 30, 96^3 re-solves",
+                      "network": "4 -> 128 x 4 -> 1 SiLU"}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,14 +231,20 @@ def main() -> int:
     ap.add_argument("--batched", type=int, default=0, metavar="N",
                     help="only the batched sweep of N uneven two-sphere instances against sequential runs")
     ap.add_argument("--autotune", action="store_true", help="autotune each instance of the batched sweep")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="only the bridge-force surrogate: sweep, GPU training, 1000-sphere run with re-solves")
+    ap.add_argument("--surrogate-seeds", type=int, default=4, help="64-bridge sweeps of training data")
+    ap.add_argument("--surrogate-steps", type=int, default=1000, help="rigid-body steps (judged every 100)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 5)
     if args.batched:
         return batched_sweep(args)
+    if args.surrogate:
+        return surrogate_run(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -194,9 +194,12 @@ def bridge_pair(shape, r1: float, r2: float, gap: float, liquid_fraction: float,
     """Two spheres of radii r1, r2 on the x axis with a surface gap, joined by a tanh-smoothed
     cylindrical bridge of liquid volume V_L = c V_S / (1 - c), c the liquid fraction
     V_L / (V_L + V_S) of Sec. 2.2 and V_S the two spheres' volume; the bridge radius is found by
-    bisection (capped at the smaller radius)."""
+    bisection (capped at the smaller radius).  rho_v_init, when given, replaces the flat-interface
+    vapour density as the initial vapour (BRIDGE_VAPOUR gives the reason)."""
     nz, ny, nx = shape
     rv, rl = coexistence_densities()
+    if rho_v_init is not None:
+        rv = float(rho_v_init)
     cy, cz = ny / 2.0, nz / 2.0
     c1 = (nx / 2.0 - gap / 2.0 - r1, cy, cz)
     c2 = (nx / 2.0 + gap / 2.0 + r2, cy, cz)
@@ -261,14 +264,15 @@ def bridge_sweep(n: int = 64, seed: int = 0, **over) -> list:
             for q in bridge_sweep_params(n, seed)]
 
 
-# Initial vapour density for isolated bridges in large vapour boxes.  Sec. 2 neglects evaporation
-# (the liquid volume is taken as constant), but a pseudopotential bridge exchanges mass with the
-# vapour until the vapour reaches the density in equilibrium with the bridge.  For the two-sphere
-# sweep that density is near 0.128, above the flat-interface value 0.119: started at 0.119, bridges
-# below about 8000 liquid cells evaporate within about 1000 steps in boxes of 48^3..128^3, while
-# started at 0.128 bridges above about 4000 cells keep their volume within a few per cent over
-# 2000 steps.
-BRIDGE_VAPOUR = 0.128
+# Initial vapour density of isolated two-sphere bridges in large vapour boxes.  Sec. 2 neglects
+# evaporation and takes the liquid volume as constant.  In the pseudopotential fluid, wetting
+# spheres started in vapour at the flat-interface density (0.119) draw the liquid of small bridges
+# into adsorbed layers on their surfaces: bridges below about 8000 liquid cells drain to zero
+# force within about 1000 steps in boxes of 48^3..128^3.  Started at 0.136 (measured, two-sphere
+# sweep and 96^3 pairs, theta 0..60 degrees), bridges down to about 800 cells at gaps up to about
+# 4 cells keep their force over 2000 steps, the force of large bridges moves by under 10 %, and
+# no bridge condenses between spheres without liquid; thin bridges across wider gaps still break.
+BRIDGE_VAPOUR = 0.136
 
 
 def tetrahedron_drop(n: int = 256, radius: float = 24.0, gap: float = 4.0, liquid_fraction: float = 0.05,
