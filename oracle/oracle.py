@@ -30,6 +30,7 @@ class _Config(C.Structure):
         ("RA", C.c_double),
         ("fext", C.c_double * 3),
         ("kinetics", C.c_int32), ("motion", C.c_int32), ("repulsion", C.c_int32),
+        ("lattice", C.c_int32),
     ]
 
 
@@ -80,6 +81,8 @@ def _load():
         lib.or_set_f.argtypes = [C.c_void_p, dp]
         lib.or_get_mask.argtypes = [C.c_void_p, ip, ip]
         lib.or_get_lattice.argtypes = [C.c_void_p, ip, dp]
+        lib.or_num_velocities.argtypes = [C.c_void_p]
+        lib.or_num_velocities.restype = C.c_int32
         lib.or_get_bodies.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         lib.or_get_force_parts.argtypes = [C.c_void_p, dp, dp, dp]
         lib.or_get_body_consts.argtypes = [C.c_void_p, dp, dp, dp]
@@ -127,6 +130,7 @@ class Oracle:
         for d in range(3):
             cfg.fext[d] = float(params["fext"][d])
         cfg.kinetics, cfg.motion, cfg.repulsion = int(params["kinetics"]), int(params["motion"]), int(params["repulsion"])
+        cfg.lattice = int(params.get("lattice", 19))
         barr = (_Body * max(nb, 1))()
         for i, b in enumerate(bodies):
             barr[i].mass_density = float(b["mass_density"])
@@ -180,20 +184,24 @@ class Oracle:
         self._lib.or_get_mask(self._h, _iptr(solid), _iptr(owner))
         return solid.reshape(self.shape), owner.reshape(self.shape)
 
+    @property
+    def q(self) -> int:
+        return int(self._lib.or_num_velocities(self._h))
+
     def populations(self) -> np.ndarray:
-        out = np.empty(19 * self.N)
+        out = np.empty(self.q * self.N)
         self._lib.or_get_f(self._h, _dptr(out))
-        return out.reshape(self.shape + (19,))
+        return out.reshape(self.shape + (self.q,))
 
     def set_populations(self, f: np.ndarray) -> None:
         a = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
         self._lib.or_set_f(self._h, _dptr(a))
 
     def lattice(self):
-        c = np.empty(57, dtype=np.int32)
-        w = np.empty(19)
+        c = np.empty(3 * self.q, dtype=np.int32)
+        w = np.empty(self.q)
         self._lib.or_get_lattice(self._h, _iptr(c), _dptr(w))
-        return c.reshape(19, 3), w
+        return c.reshape(self.q, 3), w
 
     def psi(self) -> np.ndarray:
         out = np.empty(self.N)
@@ -207,7 +215,7 @@ class Oracle:
 
     def equilibrium(self, rho: float, u) -> np.ndarray:
         uu = np.asarray(u, dtype=np.float64)
-        out = np.empty(19)
+        out = np.empty(self.q)
         self._lib.or_equilibrium(self._h, float(rho), _dptr(uu), _dptr(out))
         return out
 

@@ -24,7 +24,7 @@ def make_config(params: dict, n_bodies: int, precision: str):
     cfg = B.PfLbmConfig()
     cfg.struct_size = C.sizeof(B.PfLbmConfig)
     cfg.nx, cfg.ny, cfg.nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
-    cfg.lattice = B.PF_LBM_D3Q19
+    cfg.lattice = int(params.get("lattice", B.PF_LBM_D3Q19))
     cfg.precision = {"fp64": B.PF_LBM_FP64, "fp32": B.PF_LBM_FP32, "fp16": B.PF_LBM_FP16_STORE}[precision]
     cfg.flags = ((B.PF_LBM_KINETICS if params["kinetics"] else 0) | (B.PF_LBM_MOTION if params["motion"] else 0)
                  | (B.PF_LBM_REPULSION if params["repulsion"] else 0))

@@ -9,7 +9,8 @@ Values the paper does not give are readings:
   * sigma_ab: solid/fluid 1.0, solid/solid 0.5 (grain-boundary energy below the surface
     energy, Sec. 4.3.1); units folded into the mobility.
   * e0 (repulsion strength): 0.05.
-  * the named workloads run tau = 1.0 on a D3Q19 lattice.
+  * the named workloads run tau = 1.0 on a D3Q19 lattice (Sec. 3.2.1 prints D3Q27, which is
+    available as lattice = 27).
 """
 from __future__ import annotations
 
@@ -36,6 +37,7 @@ def paper_params(nx: int, ny: int, nz: int, nb: int) -> dict:
         "RA": 1.0,
         "fext": (0.0, 0.0, 0.0),
         "kinetics": 1, "motion": 1, "repulsion": 1,
+        "lattice": 19,
     }
 
 

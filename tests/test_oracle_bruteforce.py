@@ -43,6 +43,18 @@ def d3q19():
     return c, w, opp
 
 
+def d3q27():
+    """Every c in {-1, 0, 1}^3, with the tensor-product weights w(c) = w1(c_x) w1(c_y) w1(c_z),
+    w1(0) = 2/3, w1(+-1) = 1/6 (which gives 8/27, 2/27, 1/54, 1/216 by shell)."""
+    c19, _, _ = d3q19()
+    corners = [(a, b, d) for a in (1, -1) for b in (1, -1) for d in (1, -1)]
+    c = np.concatenate([c19, np.array(corners, dtype=np.int64)])
+    w1 = {0: 2.0 / 3.0, 1: 1.0 / 6.0, -1: 1.0 / 6.0}
+    w = np.array([w1[int(a)] * w1[int(b)] * w1[int(d)] for a, b, d in c])
+    opp = np.array([int(np.where((c == -ci).all(axis=1))[0][0]) for ci in c])
+    return c, w, opp
+
+
 def mimg(d, L):
     return d - L * np.floor(d / L + 0.5)
 
@@ -52,7 +64,8 @@ class Brute:
         self.p = p
         self.nz, self.ny, self.nx = rho0.shape
         self.n = np.array([self.nx, self.ny, self.nz])
-        self.c, self.w, self.opp = d3q19()
+        self.c, self.w, self.opp = d3q27() if p.get("lattice", 19) == 27 else d3q19()
+        self.q = len(self.w)
         self.nb = len(bodies)
         self.phi = phi0.copy()
         self.rho_s = np.array([b["mass_density"] for b in bodies])
@@ -80,7 +93,7 @@ class Brute:
                     I[i, j] = (self.rho_s[b] * ph * ((i == j) * (r ** 2).sum(-1) - r[..., i] * r[..., j])).sum()
             self.Iinv[b] = np.linalg.inv(I)
         self.solid, self.owner = self.classify()
-        self.f = np.zeros(rho0.shape + (19,))
+        self.f = np.zeros(rho0.shape + (self.q,))
         for idx in np.ndindex(rho0.shape):
             if not self.solid[idx]:
                 self.f[idx] = self.feq(rho0[idx], np.zeros(3))
@@ -122,7 +135,7 @@ class Brute:
             if self.solid[z, y, x]:
                 continue
             acc = np.zeros(3)
-            for i in range(1, 19):
+            for i in range(1, self.q):
                 n = self.wrap(x + self.c[i, 0], y + self.c[i, 1], z + self.c[i, 2])
                 acc += self.w[i] * psi[n] * self.c[i]
                 if self.solid[n]:
@@ -147,7 +160,7 @@ class Brute:
             if self.solid[z, y, x]:
                 continue
             fn[z, y, x, 0] += fs[z, y, x, 0]
-            for i in range(1, 19):
+            for i in range(1, self.q):
                 d = self.wrap(x + self.c[i, 0], y + self.c[i, 1], z + self.c[i, 2])
                 if not self.solid[d]:
                     fn[d + (i,)] += fs[z, y, x, i]
@@ -287,8 +300,10 @@ def _inputs():
     return p, bodies, rho, phi
 
 
-def test_whole_step_matches_brute_force(oracle_mod):
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_whole_step_matches_brute_force(oracle_mod, lattice):
     p, bodies, rho, phi = _inputs()
+    p["lattice"] = lattice
     bf = Brute(p, bodies, rho, phi)
     o = oracle_mod.Oracle(p, bodies, rho, phi)
     c_or, _ = o.lattice()

@@ -13,12 +13,19 @@ from oracle_helpers import body, params, slab_phi
 from pflbm_inputs import uniform_fluid
 
 
-def test_lattice_moment_identities(oracle_mod):
-    w = uniform_fluid((2, 2, 2))
+LATTICES = [19, 27]
+
+
+@pytest.mark.parametrize("lattice", LATTICES)
+def test_lattice_moment_identities(oracle_mod, lattice):
+    w = uniform_fluid((2, 2, 2), lattice=lattice)
     o = oracle_mod.Oracle(w.params, w.bodies, w.rho0, w.phi0)
     c, wt = o.lattice()
-    assert len({tuple(v) for v in c}) == 19
-    assert all((v ** 2).sum() <= 2 for v in c)
+    assert len({tuple(v) for v in c}) == lattice
+    assert all((v ** 2).sum() <= (3 if lattice == 27 else 2) for v in c)
+    # sixth moment along the body diagonal tells the two sets apart: D3Q27's weights are the
+    # tensor product of the 1-D weights (2/3, 1/6, 1/6), so sum w cx^2 cy^2 cz^2 = (1/3)^3
+    assert abs((wt * c[:, 0] ** 2 * c[:, 1] ** 2 * c[:, 2] ** 2).sum() - (1 / 27 if lattice == 27 else 0)) < 1e-15
     assert abs(wt.sum() - 1.0) < 1e-15
     assert np.allclose((wt[:, None] * c).sum(0), 0.0, atol=1e-16)
     I = np.eye(3)
@@ -30,10 +37,11 @@ def test_lattice_moment_identities(oracle_mod):
         assert abs((wt * c[:, a] * c[:, b] * c[:, cc] * c[:, d]).sum() - want) < 1e-15
 
 
+@pytest.mark.parametrize("lattice", LATTICES)
 @pytest.mark.parametrize("u", [(0.0, 0.0, 0.0), (0.05, -0.02, 0.01), (-0.1, 0.07, 0.03)])
-def test_equilibrium_moments(oracle_mod, u):
+def test_equilibrium_moments(oracle_mod, u, lattice):
     """The second-order equilibrium reproduces rho, rho u and rho (c_s^2 I + u u) exactly."""
-    w = uniform_fluid((2, 2, 2))
+    w = uniform_fluid((2, 2, 2), lattice=lattice)
     o = oracle_mod.Oracle(w.params, w.bodies, w.rho0, w.phi0)
     c, _ = o.lattice()
     rho = 1.3
@@ -67,16 +75,17 @@ def test_guo_uniform_force_momentum(oracle_mod):
     assert np.allclose(o.rho(), 1.0, atol=1e-14)
 
 
-def test_shear_wave_decay_rate(oracle_mod):
+@pytest.mark.parametrize("lattice,tau", [(19, 0.8), (27, 1.1)])
+def test_shear_wave_decay_rate(oracle_mod, lattice, tau):
     """With G = 0 a transverse shear wave decays at nu k^2, nu = c_s^2 (tau - 1/2) (BGK viscosity);
     the lattice correction is O(k^2) relative, far below the 1 % tolerance at k = 2 pi / 64."""
-    L, tau, U = 64, 0.8, 1e-3
+    L, U = 64, 1e-3
     shape = (1, L, 1)
-    w = uniform_fluid(shape, rho=1.0, G=0.0, tau=tau)
+    w = uniform_fluid(shape, rho=1.0, G=0.0, tau=tau, lattice=lattice)
     o = oracle_mod.Oracle(w.params, w.bodies, w.rho0, w.phi0)
     y = np.arange(L)
     k = 2 * math.pi / L
-    f = np.stack([o.equilibrium(1.0, (U * math.sin(k * yy), 0.0, 0.0)) for yy in y]).reshape(1, L, 1, 19)
+    f = np.stack([o.equilibrium(1.0, (U * math.sin(k * yy), 0.0, 0.0)) for yy in y]).reshape(1, L, 1, lattice)
     o.set_populations(f)
 
     def amp():
@@ -92,7 +101,8 @@ def test_shear_wave_decay_rate(oracle_mod):
     assert abs(rate / (nu * k * k) - 1.0) < 1e-2
 
 
-def test_poiseuille_exact_at_magic_tau(oracle_mod):
+@pytest.mark.parametrize("lattice", LATTICES)
+def test_poiseuille_exact_at_magic_tau(oracle_mod, lattice):
     """Body-force-driven channel flow between half-way bounce-back walls: the BGK steady state is
     the exact parabola u(z) = g (z - z0)(z1 - z) / (2 nu rho) with walls half-way between the
     solid and fluid nodes when (tau - 1/2)^2 = 3/16."""
@@ -100,7 +110,7 @@ def test_poiseuille_exact_at_magic_tau(oracle_mod):
     shape = (H + 1, 1, 2)
     tau = 0.5 + math.sqrt(3.0 / 16.0)
     g = 1e-6
-    p = params(shape, 1, tau=tau, G=0.0, fext=(g, 0.0, 0.0), kinetics=0, motion=0, repulsion=0)
+    p = params(shape, 1, tau=tau, G=0.0, fext=(g, 0.0, 0.0), kinetics=0, motion=0, repulsion=0, lattice=lattice)
     phi = slab_phi(shape, [0])[None]
     o = oracle_mod.Oracle(p, [body()], np.ones(shape), phi)
     o.step(6000)
@@ -113,14 +123,15 @@ def test_poiseuille_exact_at_magic_tau(oracle_mod):
     assert abs(rho[0]) == 0.0
 
 
-def test_couette_linear_profile_moving_wall(oracle_mod):
+@pytest.mark.parametrize("lattice", LATTICES)
+def test_couette_linear_profile_moving_wall(oracle_mod, lattice):
     """Two walls, one moving tangentially with U: the steady state is the exact linear profile
     from U to 0 between the half-way wall positions (moving-wall bounce-back, Sec. 3.2.2)."""
     H = 7
     nz = 2 * H + 2
     shape = (nz, 1, 3)
     U = 1e-3
-    p = params(shape, 2, tau=1.0, G=0.0, kinetics=0, motion=0, repulsion=0)
+    p = params(shape, 2, tau=1.0, G=0.0, kinetics=0, motion=0, repulsion=0, lattice=lattice)
     phi = np.stack([slab_phi(shape, [0]), slab_phi(shape, [H + 1])])
     o = oracle_mod.Oracle(p, [body(v=(U, 0, 0)), body()], np.ones(shape), phi)
     o.step(6000)

@@ -20,23 +20,24 @@ def _pressure(rho):
     return CS2 * rho + 0.5 * CS2 * G * psi ** 2
 
 
-def _slab(oracle_mod, L=64, steps=8000):
+def _slab(oracle_mod, L=64, steps=8000, **over):
     rv, rl = coexistence_densities(G)
     x = np.arange(L)
     d = np.abs(x - (L - 1) / 2.0) - L / 4.0
     rho = liquid_density(d, rl, rv, 4.0).reshape(1, 1, L)
-    w = uniform_fluid((1, 1, L), G=G)
+    w = uniform_fluid((1, 1, L), G=G, **over)
     o = oracle_mod.Oracle(w.params, [], rho, w.phi0)
     o.step(steps)
     return o.rho()[0, 0], o
 
 
-def test_flat_interface_coexistence(oracle_mod):
+@pytest.mark.parametrize("lattice,tau", [(19, 1.0), (27, 1.1)])
+def test_flat_interface_coexistence(oracle_mod, lattice, tau):
     """A flat liquid slab relaxes to the liquid density the paper's parameter table prints for
     G = -5 (1.888, Sec. 3.3), and its two bulks have equal equation-of-state pressure (mechanical
     equilibrium).  The continuum equal-area rule (about 1.93 / 0.156) is only approximate on
     the lattice."""
-    r, _ = _slab(oracle_mod)
+    r, _ = _slab(oracle_mod, lattice=lattice, tau=tau)
     L = r.size
     rho_l, rho_v = r[L // 2], r[0]
     assert abs(rho_l - 1.888) < 1e-3
@@ -45,13 +46,13 @@ def test_flat_interface_coexistence(oracle_mod):
     assert abs(rho_l / rl_ea - 1) < 0.03
 
 
-def _drop_dp(oracle_mod, R, n=48, steps=4000):
+def _drop_dp(oracle_mod, R, n=48, steps=4000, **over):
     rv, rl = coexistence_densities(G)
     y, x = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="ij")
     c = (n - 1) / 2.0
     d = np.sqrt((x - c) ** 2 + (y - c) ** 2) - R
     rho = liquid_density(d, rl, rv, 4.0).reshape(1, n, n)
-    w = uniform_fluid((1, n, n), G=G)
+    w = uniform_fluid((1, n, n), G=G, **over)
     o = oracle_mod.Oracle(w.params, [], rho, w.phi0)
     o.step(steps)
     r = o.rho()[0]
@@ -84,3 +85,23 @@ def test_laplace_law_and_surface_tension(oracle_mod):
     # the paper's profile-integral value for G = -5 is 3.297e-2 (Sec. 4.1); the flat profile
     # depends on the lattice only through its (shared) second and fourth moments
     assert abs(sigma_profile / 3.297e-2 - 1) < 0.01
+
+
+@pytest.mark.slow
+def test_d3q27_surface_tension_against_the_paper(oracle_mod):
+    """On the paper's own lattice and relaxation time (D3Q27, tau = 1.1, G = -5, Sec. 4.1): the
+    profile integral of a flat interface gives the paper's 3.297e-2 within 1 %, and the Laplace fit
+    of cylindrical drops the paper's 3.583e-2 within 10 % (the paper's two estimates themselves
+    differ by 8 %); the two estimates here agree within 3 %."""
+    radii = [8.0, 10.0, 12.0, 15.0]
+    dps = np.array([_drop_dp(oracle_mod, R, lattice=27, tau=1.1) for R in radii])
+    inv = 1.0 / np.array(radii)
+    A = np.vstack([inv, np.ones_like(inv)]).T
+    (slope, icpt), *_ = np.linalg.lstsq(A, dps, rcond=None)
+    r, _ = _slab(oracle_mod, lattice=27, tau=1.1)
+    psi = 1.0 - np.exp(-r)
+    dpsi = 0.5 * (np.roll(psi, -1) - np.roll(psi, 1))
+    sigma_profile = -0.5 * CS2 * CS2 * G * (dpsi ** 2).sum() / 2.0
+    assert abs(sigma_profile / 3.297e-2 - 1) < 0.01
+    assert abs(slope / 3.583e-2 - 1) < 0.10
+    assert abs(sigma_profile / slope - 1) < 0.03
