@@ -51,18 +51,18 @@ MASK_BYTES = 4  # one 32-bit cell word per node
 FORMS = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4)}
 
 
-def step_bytes_per_cell(pop: int, arith: int) -> float:
-    """Algorithmic bytes of one coupled step per node: 19 populations read and written, the
+def step_bytes_per_cell(pop: int, arith: int, q: int = 19) -> float:
+    """Algorithmic bytes of one coupled step per node: q populations read and written, the
     pseudopotential written once and read once, the cell word read once (the phase-field work on
     the box around the bodies is not counted)."""
-    return 2 * 19 * pop + 2 * arith + MASK_BYTES
+    return 2 * q * pop + 2 * arith + MASK_BYTES
 
 
-def kernel_bytes(n_fluid: int, n_solid: int, pop: int, arith: int) -> float:
-    """Algorithmic bytes of one collide-stream launch: a fluid node reads and writes its 19
+def kernel_bytes(n_fluid: int, n_solid: int, pop: int, arith: int, q: int = 19) -> float:
+    """Algorithmic bytes of one collide-stream launch: a fluid node reads and writes its q
     populations and reads its own pseudopotential and cell word (neighbour values are re-reads
     of the same arrays); a solid node reads its cell word only."""
-    return n_fluid * (2 * 19 * pop + arith + MASK_BYTES) + n_solid * float(MASK_BYTES)
+    return n_fluid * (2 * q * pop + arith + MASK_BYTES) + n_solid * float(MASK_BYTES)
 
 
 def copy_calibration(mib: int, reps: int) -> int:
@@ -223,6 +223,7 @@ def main() -> int:
     ap.add_argument("--workload", default="two_spheres_bridge")
     ap.add_argument("--n", type=int, default=None, help="grid size override (cubic)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"])
+    ap.add_argument("--lattice", type=int, default=19, choices=[19, 27], help="velocity set (27: Sec. 3.2.1)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16-storage comparison")
@@ -254,7 +255,10 @@ def main() -> int:
     from pflbm_inputs import make_workload
 
     kw = {"n": args.n} if args.n else {}
+    if args.lattice != 19:
+        kw["lattice"] = args.lattice
     w = make_workload(args.workload, **kw)
+    q = args.lattice
     pop, arith = FORMS[args.precision]
     log(f"workload {w.name} {w.shape} bodies={len(w.bodies)} {args.precision}")
     sim = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=args.precision)
@@ -272,7 +276,7 @@ def main() -> int:
     ms = start.elapsed_time(end)
     ms_per_step = ms / args.steps
     mlups = w.cells * args.steps / (ms / 1e3) / 1e6
-    pct_step = mlups * 1e6 * step_bytes_per_cell(pop, arith) / (HBM_PEAK_GBS * 1e9)
+    pct_step = mlups * 1e6 * step_bytes_per_cell(pop, arith, q) / (HBM_PEAK_GBS * 1e9)
     log(f"timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), {mlups:.1f} MLUPS")
 
     # dominant kernel: mean launch time from events recorded around it on the library's stream
@@ -282,10 +286,10 @@ def main() -> int:
     solid = sim.field("solid").sum().item()
     n_solid = int(solid)
     n_fluid = w.cells - n_solid
-    kb = kernel_bytes(n_fluid, n_solid, pop, arith)
+    kb = kernel_bytes(n_fluid, n_solid, pop, arith, q)
     achieved = kb / (tm["kernel_ms"] / 1e3) / 1e9
     sha = source_sha()
-    traffic = traffic_from_profile(w.name, args.precision, sha)
+    traffic = traffic_from_profile(w.name, args.precision, sha) if q == 19 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL,
                 "kernel_ms": round(tm["kernel_ms"], 5), "bytes_per_launch": kb}
@@ -311,7 +315,7 @@ def main() -> int:
         hm = w.cells * args.steps / (hms / 1e3) / 1e6
         forms = {"fp16_store": {"value": round(hm, 2), "unit": "MLUPS", "ms_per_step": round(hms / args.steps, 5),
                                 "vs_fp32": round(hm / mlups, 3),
-                                "pct_hbm_step_algorithmic": round(hm * 1e6 * step_bytes_per_cell(*FORMS["fp16"])
+                                "pct_hbm_step_algorithmic": round(hm * 1e6 * step_bytes_per_cell(*FORMS["fp16"], q)
                                                                   / (HBM_PEAK_GBS * 1e9), 4)}}
         log(f"fp16 storage: {hm:.1f} MLUPS ({hm / mlups:.2f}x fp32)")
         del h
@@ -324,7 +328,7 @@ def main() -> int:
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16-store/f32"}[args.precision], "data": "synthetic",
-        "config": {"workload": f"{w.name} {w.shape[2]}x{w.shape[1]}x{w.shape[0]} D3Q19, {len(w.bodies)} bodies, "
+        "config": {"workload": f"{w.name} {w.shape[2]}x{w.shape[1]}x{w.shape[0]} D3Q{q}, {len(w.bodies)} bodies, "
                                f"motion+kinetics on", "cells": w.cells, "precision": args.precision},
         "pct_hbm_step_algorithmic": round(pct_step, 4),
         "roofline": roofline,

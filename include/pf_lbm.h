@@ -49,7 +49,9 @@ enum {
     PF_LBM_ENONFINITE = -5,   /* non-finite body force or state, or advection CFL above 1   */
 };
 
-enum { PF_LBM_D3Q19 = 19 };
+/* Velocity sets: D3Q19 (the named workloads) and D3Q27, the set printed in Sec. 3.2.1 (weights
+ * 8/27, 2/27, 1/54, 1/216 by speed shell).  Both have c_s^2 = 1/3. */
+enum { PF_LBM_D3Q19 = 19, PF_LBM_D3Q27 = 27 };
 
 /* Arithmetic and storage of the fluid populations.  FP64 and FP32 store and compute in that
  * type.  FP16_STORE stores each population f_i(x) as an FP16 deviation from its equilibrium
@@ -84,7 +86,7 @@ enum { PF_LBM_DST_F64 = 0, PF_LBM_DST_F32 = 1 };
 typedef struct {
     uint32_t struct_size;   /* sizeof(pf_lbm_config): ABI check                                  */
     int32_t nx, ny, nz;     /* periodic box, cells per axis (each >= 1)                          */
-    int32_t lattice;        /* PF_LBM_D3Q19                                                       */
+    int32_t lattice;        /* PF_LBM_D3Q19 or PF_LBM_D3Q27                                       */
     int32_t precision;      /* PF_LBM_FP64, PF_LBM_FP32 or PF_LBM_FP16_STORE                      */
     int32_t flags;          /* PF_LBM_KINETICS | PF_LBM_MOTION | PF_LBM_REPULSION                 */
     double tau;             /* BGK relaxation time, > 1/2 (Sec. 3.2.1)                            */
@@ -123,7 +125,7 @@ typedef struct {
  *   hip_stream: hipStream_t the handle is bound to (NULL = default stream).
  *   out: receives the handle (owned by the caller, released with pf_lbm_destroy).
  * Errors: PF_LBM_EINVAL (bad sizes or parameters), PF_LBM_ENOMEM (ws_bytes too small),
- *   PF_LBM_EUNSUPPORTED (lattice other than D3Q19, precision other than FP64/FP32),
+ *   PF_LBM_EUNSUPPORTED (lattice other than D3Q19/D3Q27, precision other than FP64/FP32/FP16_STORE),
  *   PF_LBM_EDEVICE (HIP failure).  The call returns after the initial fields are on the device.
  */
 int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *bodies, const double *rho0,

@@ -1,5 +1,5 @@
 // Device-side building blocks of the coupled phase-field / lattice-Boltzmann step for gfx950:
-// the D3Q19 velocity set as compile-time constants, the mask byte layout, the body table and
+// the D3Q19 and D3Q27 velocity sets as compile-time constants, the mask byte layout, the body table and
 // the per-step state shared by the kernels, wave64 reductions and the XCD-aware block order.
 #pragma once
 
@@ -12,20 +12,35 @@
 
 namespace pfl {
 
-// ---- D3Q19 (Sec. 3.2.1 prints D3Q27; both share c_s^2 = 1/3 and the second and fourth
-// moments).  Direction pairs (2k-1, 2k) are opposite.  Rest, 6 faces, 12 edges.
-constexpr int kCX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int kCY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int kCZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+// ---- velocity sets.  Sec. 3.2.1 prints D3Q27; the named workloads run D3Q19 (both share
+// c_s^2 = 1/3 and the second and fourth moments).  One direction table serves both: the rest
+// direction, 6 faces, 12 edges (the D3Q19 set), then the 8 corners; pairs (2k-1, 2k) are
+// opposite.  Weights by speed shell |c|^2 = 0..3.
+constexpr int kCX[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int kCY[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int kCZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, 1, -1};
 
-template <int I>
+struct D3Q19 {
+    static constexpr int Q = 19;
+    // the cell word carries one solid-neighbour bit per direction
+    static constexpr bool kBits = true;
+    static constexpr double wshell[4] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0, 0.0};
+};
+struct D3Q27 {
+    static constexpr int Q = 27;
+    // 26 neighbour bits do not fit beside the flags: kernels read the neighbours' words instead
+    static constexpr bool kBits = false;
+    static constexpr double wshell[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+};
+
+template <int I, class L = D3Q19>
 struct Dir {
     static constexpr int x = kCX[I], y = kCY[I], z = kCZ[I];
     static constexpr int opp = I == 0 ? 0 : ((I & 1) ? I + 1 : I - 1);
     static constexpr int c2 = x * x + y * y + z * z;
     template <typename T>
     __device__ static constexpr T w() {
-        return c2 == 0 ? T(1.0 / 3.0) : (c2 == 1 ? T(1.0 / 18.0) : T(1.0 / 36.0));
+        return T(L::wshell[c2]);
     }
 };
 
@@ -41,7 +56,7 @@ __device__ __forceinline__ void sfor(F &&f) {
 
 // ---- cell word (one uint32 per node): bit 31 solid, bit 30 became solid this step, bit 29
 // became fluid this step, bits 24-28 owning body of a solid node, bit i (1..18) set when the
-// neighbour in direction i is solid (kept current inside the body box by k_neighbour_bits)
+// neighbour in direction i is solid (D3Q19 only; kept current inside the body box by k_post)
 using cell_t = uint32_t;
 constexpr uint32_t C_SOLID = 1u << 31, C_F2S = 1u << 30, C_S2F = 1u << 29, C_NBMASK = 0x7FFFEu;
 __device__ __forceinline__ int owner_of(uint32_t w) { return (int)((w >> 24) & 31u); }

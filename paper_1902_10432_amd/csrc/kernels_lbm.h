@@ -9,7 +9,7 @@ namespace pfl {
 // Pseudopotential psi = 1 - exp(-rho/rho0) of every fluid node; a solid node carries the value
 // of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.
 // psi_ref: the pseudopotential of the previous step (reference density of the FP16 form).
-template <typename S>
+template <typename S, class L>
 __global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, const S *__restrict__ f, const cell_t *__restrict__ mask,
                                              const BodyDev *__restrict__ bodies, const ArT<S> *__restrict__ psi_ref,
                                              ArT<S> *__restrict__ psi) {
@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, const S *__restrict_
         // the weights sum to one: rho = R + sum of the stored deviations in the FP16 form
         T r = T(0);
         if constexpr (sizeof(S) == 2) r = ref_density(psi_ref[idx], p.rho0);
-        sfor<19>([&](auto I) { r += (T)f[(long long)I * p.Np + idx]; });
+        sfor<L::Q>([&](auto I) { r += (T)f[(long long)I * p.Np + idx]; });
         out = -expm1(-r * p.inv_rho0);
     }
     psi[idx] = out;
@@ -125,7 +125,7 @@ __device__ __forceinline__ bool cell_of_block(int nx, int ny, int &x, int &y, in
 //   f*_i = (1 - 1/tau) f_i + w (even + odd),  f*_opp = (1 - 1/tau) f_opp + w (even - odd),
 //   even = rho/tau (1 - 3/2 v.v) - 3 g v.F + 9/2 rho/tau cu^2 + 9 g cu cF,  odd = 3 rho/tau cu + 3 g cF,
 // g = 1 - 1/(2 tau), which is the BGK relaxation to the second-order equilibrium plus the Guo term.
-template <typename S>
+template <typename S, class L>
 __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *__restrict__ fin, S *__restrict__ fout,
                                                         const ArT<S> *__restrict__ psi,
                                                         const ArT<S> *__restrict__ psi_prev,
@@ -142,7 +142,19 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
     const cell_t w0 = mask[idx];
     if (w0 & C_SOLID) return;
-    const uint32_t solid_dirs = w0 & C_NBMASK;
+    // bit i: the neighbour in direction i is solid (D3Q19: kept in the word; D3Q27: read here)
+    uint32_t solid_dirs = 0;
+    if constexpr (L::kBits) {
+        solid_dirs = w0 & C_NBMASK;
+    } else {
+        const NbrU nm(x, y, z, nx, ny, nz, (int)sizeof(cell_t));
+        const uint32_t im = idx * (uint32_t)sizeof(cell_t);
+        sfor<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0)
+                if (ldb(mask, nm.template at<i>(im)) & C_SOLID) solid_dirs |= 1u << i;
+        });
+    }
     const uint32_t ib = idx * (uint32_t)sizeof(T);      // psi (arithmetic type)
     const uint32_t is = idx * (uint32_t)sizeof(S);      // populations (storage type)
     const NbrU nb(x, y, z, nx, ny, nz, (int)sizeof(T));
@@ -150,31 +162,31 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     const long long Np = p.Np;
     constexpr bool H = sizeof(S) == 2;  // FP16 storage: deviations from w_i R
 
-    T f[19];
+    T f[L::Q];
     {
         const T rin = H ? ref_density(psi_prev[idx], p.rho0) : T(0);  // reference of the inputs
-        sfor<19>([&](auto I) {
-            f[I] = pop_get<S>(ldb(fin + (long long)I * Np, is), Dir<decltype(I)::value>::template w<T>() * rin);
+        sfor<L::Q>([&](auto I) {
+            f[I] = pop_get<S>(ldb(fin + (long long)I * Np, is), Dir<decltype(I)::value, L>::template w<T>() * rin);
         });
     }
     // moments from pair sums and differences
     T rho = f[0], jx = T(0), jy = T(0), jz = T(0);
-    sfor<9>([&](auto K) {
+    sfor<(L::Q - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;  // i and i + 1 are opposite
         const T sp = f[i] + f[i + 1], dm = f[i] - f[i + 1];
         rho += sp;
-        if constexpr (Dir<i>::x == 1) jx += dm;
-        if constexpr (Dir<i>::x == -1) jx -= dm;
-        if constexpr (Dir<i>::y == 1) jy += dm;
-        if constexpr (Dir<i>::y == -1) jy -= dm;
-        if constexpr (Dir<i>::z == 1) jz += dm;
-        if constexpr (Dir<i>::z == -1) jz -= dm;
+        if constexpr (Dir<i, L>::x == 1) jx += dm;
+        if constexpr (Dir<i, L>::x == -1) jx -= dm;
+        if constexpr (Dir<i, L>::y == 1) jy += dm;
+        if constexpr (Dir<i, L>::y == -1) jy -= dm;
+        if constexpr (Dir<i, L>::z == 1) jz += dm;
+        if constexpr (Dir<i, L>::z == -1) jz -= dm;
     });
 
     // pseudopotential force from pair differences of the neighbours' psi
-    T s1x = T(0), s1y = T(0), s1z = T(0), s2x = T(0), s2y = T(0), s2z = T(0);
-    T rdst[19];  // FP16 form: reference density of each push destination
-    sfor<9>([&](auto K) {
+    T s1x = T(0), s1y = T(0), s1z = T(0), s2x = T(0), s2y = T(0), s2z = T(0), s3x = T(0), s3y = T(0), s3z = T(0);
+    T rdst[L::Q];  // FP16 form: reference density of each push destination
+    sfor<(L::Q - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;
         const T pa = ldb(psi, nb.template at<i>(ib)), pb = ldb(psi, nb.template at<i + 1>(ib));
         if constexpr (H) {
@@ -182,23 +194,34 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
             rdst[i + 1] = ref_density(pb, p.rho0);
         }
         const T dp = pa - pb;
-        if constexpr (Dir<i>::c2 == 1) {
-            if constexpr (Dir<i>::x != 0) s1x += T(Dir<i>::x) * dp;
-            if constexpr (Dir<i>::y != 0) s1y += T(Dir<i>::y) * dp;
-            if constexpr (Dir<i>::z != 0) s1z += T(Dir<i>::z) * dp;
+        if constexpr (Dir<i, L>::c2 == 1) {
+            if constexpr (Dir<i, L>::x != 0) s1x += T(Dir<i, L>::x) * dp;
+            if constexpr (Dir<i, L>::y != 0) s1y += T(Dir<i, L>::y) * dp;
+            if constexpr (Dir<i, L>::z != 0) s1z += T(Dir<i, L>::z) * dp;
+        } else if constexpr (Dir<i, L>::c2 == 2) {
+            if constexpr (Dir<i, L>::x != 0) s2x += T(Dir<i, L>::x) * dp;
+            if constexpr (Dir<i, L>::y != 0) s2y += T(Dir<i, L>::y) * dp;
+            if constexpr (Dir<i, L>::z != 0) s2z += T(Dir<i, L>::z) * dp;
         } else {
-            if constexpr (Dir<i>::x != 0) s2x += T(Dir<i>::x) * dp;
-            if constexpr (Dir<i>::y != 0) s2y += T(Dir<i>::y) * dp;
-            if constexpr (Dir<i>::z != 0) s2z += T(Dir<i>::z) * dp;
+            s3x += T(Dir<i, L>::x) * dp;
+            s3y += T(Dir<i, L>::y) * dp;
+            s3z += T(Dir<i, L>::z) * dp;
         }
     });
     const T psi0 = ldb(psi, ib);
     const T gp = -p.G * psi0;
     const T rown = H ? ref_density(psi0, p.rho0) : T(0);  // reference of this node's own slots
-    const T w1 = T(1.0 / 18.0), w2 = T(1.0 / 36.0);
-    const T Fx = gp * (w1 * s1x + w2 * s2x) + p.fext[0];
-    const T Fy = gp * (w1 * s1y + w2 * s2y) + p.fext[1];
-    const T Fz = gp * (w1 * s1z + w2 * s2z) + p.fext[2];
+    const T w1 = T(L::wshell[1]), w2 = T(L::wshell[2]);
+    T Fx = w1 * s1x + w2 * s2x, Fy = w1 * s1y + w2 * s2y, Fz = w1 * s1z + w2 * s2z;
+    if constexpr (L::Q == 27) {
+        const T w3 = T(L::wshell[3]);
+        Fx += w3 * s3x;
+        Fy += w3 * s3y;
+        Fz += w3 * s3z;
+    }
+    Fx = gp * Fx + p.fext[0];
+    Fy = gp * Fy + p.fext[1];
+    Fz = gp * Fz + p.fext[2];
 
     // half-force velocity; an empty node has v = 0
     T ux = T(0), uy = T(0), uz = T(0);
@@ -211,12 +234,12 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     const T om = p.omega, g = p.guo, omr = om * rho;
     const T A = omr * (T(1) - T(1.5) * (ux * ux + uy * uy + uz * uz)) - T(3) * g * (ux * Fx + uy * Fy + uz * Fz);
     const T B = T(3) * omr, C = T(4.5) * omr, D = T(3) * g, E = T(9) * g, keep = T(1) - om;
-    f[0] = keep * f[0] + Dir<0>::template w<T>() * A;
-    sfor<9>([&](auto K) {
+    f[0] = keep * f[0] + Dir<0, L>::template w<T>() * A;
+    sfor<(L::Q - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;
-        constexpr T w = Dir<i>::template w<T>();
-        const T cu = T(Dir<i>::x) * ux + T(Dir<i>::y) * uy + T(Dir<i>::z) * uz;
-        const T cF = T(Dir<i>::x) * Fx + T(Dir<i>::y) * Fy + T(Dir<i>::z) * Fz;
+        constexpr T w = Dir<i, L>::template w<T>();
+        const T cu = T(Dir<i, L>::x) * ux + T(Dir<i, L>::y) * uy + T(Dir<i, L>::z) * uz;
+        const T cF = T(Dir<i, L>::x) * Fx + T(Dir<i, L>::y) * Fy + T(Dir<i, L>::z) * Fz;
         const T even = A + cu * (C * cu + E * cF);
         const T odd = B * cu + D * cF;
         f[i] = keep * f[i] + w * (even + odd);
@@ -225,35 +248,35 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
 
     // streaming
     if (!solid_dirs) {
-        sfor<19>([&](auto I) {
+        sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0)
-                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i>::template w<T>() * rdst[i]));
+                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
         });
-        stb(fout, is, pop_put<S>(f[0], Dir<0>::template w<T>() * rown));
+        stb(fout, is, pop_put<S>(f[0], Dir<0, L>::template w<T>() * rown));
         return;
     }
     const NbrU ne(x, y, z, nx, ny, nz, 1);
     T drho = T(0);
-    sfor<19>([&](auto I) {
+    sfor<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (i > 0) {
             if (!(solid_dirs & (1u << i))) {
-                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i>::template w<T>() * rdst[i]));
+                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
             } else {
                 // reflected into direction opp(i) with g = -2 rho w_i (c_i . u_w) / c_s^2, u_w at
                 // the link midpoint x + c_i / 2
                 const BodyDev &Bd = bodies[owner_of(mask[ne.template at<i>(idx)])];
                 double uwx, uwy, uwz;
-                wall_velocity(p, Bd, x + 0.5 * Dir<i>::x, y + 0.5 * Dir<i>::y, z + 0.5 * Dir<i>::z, uwx, uwy, uwz);
-                const double cuw = Dir<i>::x * uwx + Dir<i>::y * uwy + Dir<i>::z * uwz;
-                const T gw = T(-6.0 * Dir<i>::template w<double>() * cuw) * rho;
-                stb(fout + (long long)Dir<i>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i>::template w<T>() * rown));
+                wall_velocity(p, Bd, x + 0.5 * Dir<i, L>::x, y + 0.5 * Dir<i, L>::y, z + 0.5 * Dir<i, L>::z, uwx, uwy, uwz);
+                const double cuw = Dir<i, L>::x * uwx + Dir<i, L>::y * uwy + Dir<i, L>::z * uwz;
+                const T gw = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
+                stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
                 drho += gw;
             }
         }
     });
-    stb(fout, is, pop_put<S>(f[0] - drho, Dir<0>::template w<T>() * rown));
+    stb(fout, is, pop_put<S>(f[0] - drho, Dir<0, L>::template w<T>() * rown));
 }
 
 // Per-body force and torque sums of the step, one box node per thread (Sec. 3.1.1, 3.1.2, 3.2.2):
@@ -270,20 +293,20 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
 // also advances the bodies.
 // waves per block of the force scan (one block per CU), sized so that the gathered link values
 // stay in registers: 12 in FP32, 8 in FP64
-template <typename T>
+template <typename T, class L>
 constexpr int force_waves() {
-    return sizeof(T) == 4 ? 12 : 8;
+    return L::Q == 19 ? (sizeof(T) == 4 ? 12 : 8) : (sizeof(T) == 4 ? 8 : 4);
 }
 
-template <typename S>
-__global__ __launch_bounds__(64 * force_waves<ArT<S>>()) void k_body_forces(Prm<ArT<S>> p, int parity,
+template <typename S, class L>
+__global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces(Prm<ArT<S>> p, int parity,
                                                      const StepState *st, const S *__restrict__ fin,
                                                      const S *__restrict__ fpost, const ArT<S> *__restrict__ psi,
                                                      const ArT<S> *__restrict__ psi_prev,
                                                      const cell_t *__restrict__ mask,
                                                      const BodyDev *__restrict__ bodies, double *part) {
     using T = ArT<S>;
-    constexpr int W = force_waves<T>(), NT = 64 * W;
+    constexpr int W = force_waves<T, L>(), NT = 64 * W;
     __shared__ double acc[W][PF_LBM_MAX_BODIES][6];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nbod = p.nb;
@@ -309,8 +332,8 @@ __global__ __launch_bounds__(64 * force_waves<ArT<S>>()) void k_body_forces(Prm<
         T rho = T(0), ps0 = T(0);
         // per link i into a solid neighbour: its owner (4-bit fields) and the body-independent part
         // of the link force, a_i = 2 f_opp(i) + G psi(x) w_i psi(x + c_i)
-        uint32_t own[3] = {0u, 0u, 0u};
-        T a[19];
+        uint32_t own[(L::Q + 7) / 8] = {};
+        T a[L::Q];
         if (k < it.vol) {
             int u[3], c[3];
             it.cell(k, u, c);
@@ -321,18 +344,28 @@ __global__ __launch_bounds__(64 * force_waves<ArT<S>>()) void k_body_forces(Prm<
             const cell_t w0 = mask[idx];
             if (!(w0 & C_SOLID)) {
                 fluid = true;
-                nbits = w0 & C_NBMASK;
+                if constexpr (L::kBits) {
+                    nbits = w0 & C_NBMASK;
+                } else {
+                    const NbrU nm(x, y, z, nx, ny, nz, (int)sizeof(cell_t));
+                    const uint32_t im = (uint32_t)idx * (uint32_t)sizeof(cell_t);
+                    sfor<L::Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        if constexpr (i > 0)
+                            if (ldb(mask, nm.template at<i>(im)) & C_SOLID) nbits |= 1u << i;
+                    });
+                }
                 if (nbits) {
                     // one round of independent gathers (byte offsets from uniform bases)
                     const NbrU ne(x, y, z, nx, ny, nz, 1);
                     const uint32_t ib = (uint32_t)idx * (uint32_t)sizeof(T);
                     const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
                     rho = sizeof(S) == 2 ? ref_density(psi_prev[idx], p.rho0) : T(0);
-                    sfor<19>([&](auto I) { rho += (T)ldb(fin + (long long)I * Np, is); });
+                    sfor<L::Q>([&](auto I) { rho += (T)ldb(fin + (long long)I * Np, is); });
                     ps0 = ldb(psi, ib);
                     const T rown = sizeof(S) == 2 ? ref_density(ps0, p.rho0) : T(0);
                     const T gp = p.G * ps0;
-                    sfor<19>([&](auto I) {
+                    sfor<L::Q>([&](auto I) {
                         constexpr int i = decltype(I)::value;
                         a[i] = T(0);
                         if constexpr (i > 0) {
@@ -341,9 +374,9 @@ __global__ __launch_bounds__(64 * force_waves<ArT<S>>()) void k_body_forces(Prm<
                                 const uint32_t o = (uint32_t)owner_of(ldb(mask, n * 4u));
                                 own[i >> 3] |= o << (4 * (i & 7));
                                 touched |= 1u << o;
-                                a[i] = T(2) * pop_get<S>(ldb(fpost + (long long)Dir<i>::opp * Np, is),
-                                                         Dir<i>::template w<T>() * rown) +
-                                       gp * Dir<i>::template w<T>() * ldb(psi, n * (uint32_t)sizeof(T));
+                                a[i] = T(2) * pop_get<S>(ldb(fpost + (long long)Dir<i, L>::opp * Np, is),
+                                                         Dir<i, L>::template w<T>() * rown) +
+                                       gp * Dir<i, L>::template w<T>() * ldb(psi, n * (uint32_t)sizeof(T));
                             }
                         }
                     });
@@ -376,19 +409,19 @@ __global__ __launch_bounds__(64 * force_waves<ArT<S>>()) void k_body_forces(Prm<
             double v[6] = {0, 0, 0, 0, 0, 0};
             if ((touched & (1u << b)) && fluid) {
                 const BodyDev &B = bodies[b];
-                sfor<19>([&](auto I) {
+                sfor<L::Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     if constexpr (i > 0) {
                         if ((nbits & (1u << i)) && ((own[i >> 3] >> (4 * (i & 7))) & 15u) == (uint32_t)b) {
-                            const double px = x + 0.5 * Dir<i>::x, py = y + 0.5 * Dir<i>::y, pz = z + 0.5 * Dir<i>::z;
+                            const double px = x + 0.5 * Dir<i, L>::x, py = y + 0.5 * Dir<i, L>::y, pz = z + 0.5 * Dir<i, L>::z;
                             double uwx, uwy, uwz;
                             wall_velocity(p, B, px, py, pz, uwx, uwy, uwz);
-                            const double cuw = Dir<i>::x * uwx + Dir<i>::y * uwy + Dir<i>::z * uwz;
+                            const double cuw = Dir<i, L>::x * uwx + Dir<i, L>::y * uwy + Dir<i, L>::z * uwz;
                             // moving-wall term g; the link carries 2 f*_i + g = 2 f_opp(i) - g to the
                             // body plus the pseudopotential reaction, both along c_i
-                            const T g = T(-6.0 * Dir<i>::template w<double>() * cuw) * rho;
+                            const T g = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
                             const double s = (double)(a[i] - g);
-                            const double fx = s * Dir<i>::x, fy = s * Dir<i>::y, fz = s * Dir<i>::z;
+                            const double fx = s * Dir<i, L>::x, fy = s * Dir<i, L>::y, fz = s * Dir<i, L>::z;
                             const double rx = mimg_r(px - B.X[0], nx, p.inv_n[0]), ry = mimg_r(py - B.X[1], ny, p.inv_n[1]),
                                          rz = mimg_r(pz - B.X[2], nz, p.inv_n[2]);
                             v[0] += fx;

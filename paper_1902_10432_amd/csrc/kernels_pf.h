@@ -566,11 +566,11 @@ __global__ __launch_bounds__(256) void k_classify_init(Prm<PT> p, int parity, co
 }
 
 // Equilibrium of (rho, u) in direction i (Sec. 3.2.1)
-template <typename T, int I>
+template <typename T, int I, class L>
 __device__ __forceinline__ T feq_dir(T rho, T ux, T uy, T uz) {
-    const T cu = T(Dir<I>::x) * ux + T(Dir<I>::y) * uy + T(Dir<I>::z) * uz;
+    const T cu = T(Dir<I, L>::x) * ux + T(Dir<I, L>::y) * uy + T(Dir<I, L>::z) * uz;
     const T uu = ux * ux + uy * uy + uz * uz;
-    return Dir<I>::template w<T>() * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+    return Dir<I, L>::template w<T>() * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
 }
 
 // number of fluid nodes (current mask) within squared radius r2 of node (x, y, z), over the 26
@@ -610,7 +610,7 @@ __device__ __forceinline__ int conversion_radius(const cell_t *mask, int x, int 
 // rho_n, u_n = j_n / rho_n of the converted node's populations; a node that just became fluid
 // starts from empty populations.  Sources are only read here (k_post empties them).
 // psi: the pseudopotential of this step (reference density of the FP16 form)
-template <typename S>
+template <typename S, class L>
 __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__ mask, S *f,
                                 const ArT<S> *__restrict__ psi, int x, int y, int z, int idx, cell_t m) {
     using T = ArT<S>;
@@ -618,10 +618,10 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
     const long long Np = p.Np;
     constexpr bool H = sizeof(S) == 2;
     const T rr = H ? ref_density(psi[idx], p.rho0) : T(0);
-    T acc[19];
-    sfor<19>([&](auto I) {
+    T acc[L::Q];
+    sfor<L::Q>([&](auto I) {
         acc[I] = (m & C_S2F) ? T(0)
-                             : pop_get<S>(f[(long long)I * Np + idx], Dir<decltype(I)::value>::template w<T>() * rr);
+                             : pop_get<S>(f[(long long)I * Np + idx], Dir<decltype(I)::value, L>::template w<T>() * rr);
     });
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
@@ -634,18 +634,18 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
                 double r2;
                 const int cnt = conversion_radius(mask, sx, sy, sz, nx, ny, nz, p.R_A, r2);
                 if (cnt == 0 || d2 > r2 + 1e-9) continue;
-                T fs[19];
+                T fs[L::Q];
                 const T rn = H ? ref_density(psi[n], p.rho0) : T(0);
-                sfor<19>([&](auto I) {
-                    fs[I] = pop_get<S>(f[(long long)I * Np + n], Dir<decltype(I)::value>::template w<T>() * rn);
+                sfor<L::Q>([&](auto I) {
+                    fs[I] = pop_get<S>(f[(long long)I * Np + n], Dir<decltype(I)::value, L>::template w<T>() * rn);
                 });
                 T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
-                sfor<19>([&](auto I) {
+                sfor<L::Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     rho += fs[i];
-                    jx += T(Dir<i>::x) * fs[i];
-                    jy += T(Dir<i>::y) * fs[i];
-                    jz += T(Dir<i>::z) * fs[i];
+                    jx += T(Dir<i, L>::x) * fs[i];
+                    jy += T(Dir<i, L>::y) * fs[i];
+                    jz += T(Dir<i, L>::z) * fs[i];
                 });
                 T vx = T(0), vy = T(0), vz = T(0);
                 if (rho > T(0)) {
@@ -654,10 +654,10 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
                     vz = jz / rho;
                 }
                 const T inv = T(1) / T(cnt);
-                sfor<19>([&](auto I) { acc[I] += feq_dir<T, decltype(I)::value>(rho, vx, vy, vz) * inv; });
+                sfor<L::Q>([&](auto I) { acc[I] += feq_dir<T, decltype(I)::value, L>(rho, vx, vy, vz) * inv; });
             }
-    sfor<19>([&](auto I) {
-        f[(long long)I * Np + idx] = pop_put<S>(acc[I], Dir<decltype(I)::value>::template w<T>() * rr);
+    sfor<L::Q>([&](auto I) {
+        f[(long long)I * Np + idx] = pop_put<S>(acc[I], Dir<decltype(I)::value, L>::template w<T>() * rr);
     });
 }
 
@@ -681,7 +681,7 @@ __device__ __forceinline__ bool f2s_neighbour(const cell_t *mask, int x, int y, 
 // index among r's neighbours (so each receiver is handled once, in a fixed order of its sources),
 // and a node that became fluid with no converted neighbour is emptied.  When the list overflowed,
 // the whole box is scanned instead.
-template <typename S>
+template <typename S, class L>
 __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parity, const StepState *st,
                                                         const cell_t *__restrict__ mask, S *f,
                                                         const ArT<S> *__restrict__ psi,
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
             const cell_t m = mask[idx];
             if (m & C_SOLID) continue;
             if (!(m & C_S2F) && !f2s_neighbour(mask, c[0], c[1], c[2], nx, ny, nz, 0xFFFFFFFFu)) continue;
-            gather_receiver(p, mask, f, psi, c[0], c[1], c[2], idx, m);
+            gather_receiver<S, L>(p, mask, f, psi, c[0], c[1], c[2], idx, m);
         }
         return;
     }
@@ -715,8 +715,8 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
             const cell_t m = mask[e];
             if ((m & C_S2F) && !f2s_neighbour(mask, ex, ey, ez, nx, ny, nz, 0xFFFFFFFFu)) {
                 const T re = sizeof(S) == 2 ? ref_density(psi[e], p.rho0) : T(0);
-                sfor<19>([&](auto I) {
-                    f[(long long)I * Np + e] = pop_put<S>(T(0), Dir<decltype(I)::value>::template w<T>() * re);
+                sfor<L::Q>([&](auto I) {
+                    f[(long long)I * Np + e] = pop_put<S>(T(0), Dir<decltype(I)::value, L>::template w<T>() * re);
                 });
             }
             continue;
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
         const cell_t m = mask[r];
         if (m & C_SOLID) continue;
         if (f2s_neighbour(mask, rx, ry, rz, nx, ny, nz, e)) continue;  // a lower-index source handles r
-        gather_receiver(p, mask, f, psi, rx, ry, rz, r, m);
+        gather_receiver<S, L>(p, mask, f, psi, rx, ry, rz, r, m);
     }
 }
 
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
 // which this pass never changes, so repeated visits of one node write the same word.
 // empty: 0 never, 1 when the word carries the "became solid" mark (one visit per node), 2 always
 // (the caller knows the node became solid).
-template <typename S>
+template <typename S, class L>
 __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask, S *f, const ArT<S> *psi, int x, int y,
                                              int z, uint32_t idx, int empty, unsigned long long &lost) {
     using T = ArT<S>;
@@ -748,17 +748,19 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
         double r2;
         if (conversion_radius(mask, x, y, z, nx, ny, nz, p.R_A, r2) == 0) ++lost;
         const T rr = sizeof(S) == 2 ? ref_density(psi[idx], p.rho0) : T(0);
-        sfor<19>([&](auto I) {
-            f[(long long)I * p.Np + idx] = pop_put<S>(T(0), Dir<decltype(I)::value>::template w<T>() * rr);
+        sfor<L::Q>([&](auto I) {
+            f[(long long)I * p.Np + idx] = pop_put<S>(T(0), Dir<decltype(I)::value, L>::template w<T>() * rr);
         });
     }
-    const NbrU ne1(x, y, z, nx, ny, nz, 1);
     uint32_t bits = 0;
-    sfor<19>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (i > 0)
-            if (mask[ne1.template at<i>(idx)] & C_SOLID) bits |= 1u << i;
-    });
+    if constexpr (L::kBits) {
+        const NbrU ne1(x, y, z, nx, ny, nz, 1);
+        sfor<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0)
+                if (mask[ne1.template at<i>(idx)] & C_SOLID) bits |= 1u << i;
+        });
+    }
     const cell_t mn = (m & ~(C_F2S | C_S2F | C_NBMASK)) | bits;
     if (mn != m) mask[idx] = mn;
 }
@@ -767,7 +769,7 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
 // box node is refreshed; otherwise only the nodes whose words can have changed: each event node
 // (emptied if it became solid) and the 18 nodes that have it as a neighbour.  Without events
 // the kernel returns at once.
-template <typename S>
+template <typename S, class L>
 __global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepState *st, cell_t *__restrict__ mask, S *f,
                                               const ArT<S> *__restrict__ psi, const uint32_t *__restrict__ evlist,
                                               uint32_t evcap, int full) {
@@ -781,18 +783,21 @@ __global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepSta
         for (int k = gtid; k < it.vol; k += gstride) {
             int u[3], c[3];
             it.cell(k, u, c);
-            refresh_node(p, mask, f, psi, c[0], c[1], c[2], (uint32_t)(c[0] + nx * (c[1] + ny * c[2])), full ? 0 : 1,
+            refresh_node<S, L>(p, mask, f, psi, c[0], c[1], c[2], (uint32_t)(c[0] + nx * (c[1] + ny * c[2])), full ? 0 : 1,
                          lost);
         }
     } else {
-        for (int j = gtid; j < (int)nev * 19; j += gstride) {
-            const uint32_t ent = evlist[j / 19];
-            const int i = j % 19;
+        // D3Q19: the event node and the 18 nodes whose bit for it may change; D3Q27 keeps no
+        // bits, so only the event node itself
+        constexpr int NR = L::kBits ? L::Q : 1;
+        for (int j = gtid; j < (int)nev * NR; j += gstride) {
+            const uint32_t ent = evlist[j / NR];
+            const int i = j % NR;
             const uint32_t e = ent & 0x7FFFFFFFu;
             const int ex = (int)(e % (uint32_t)nx), ey = (int)((e / (uint32_t)nx) % (uint32_t)ny), ez = (int)(e / ((uint32_t)nx * ny));
             // node whose neighbour in direction i is e
             const int x = wrapi(ex - kCX[i], nx), y = wrapi(ey - kCY[i], ny), z = wrapi(ez - kCZ[i], nz);
-            refresh_node(p, mask, f, psi, x, y, z, (uint32_t)(x + nx * (y + ny * z)),
+            refresh_node<S, L>(p, mask, f, psi, x, y, z, (uint32_t)(x + nx * (y + ny * z)),
                          (i == 0 && (ent & 0x80000000u)) ? 2 : 0, lost);
         }
     }
@@ -816,7 +821,7 @@ __global__ void k_init_phi(Prm<T> p, const double *__restrict__ src, double *__r
 // fluid at rest: f = f_eq(rho, 0) = w_i rho on fluid nodes, 0 on solid nodes
 // fluid at rest: f = f_eq(rho, 0) = w_i rho on fluid nodes, 0 on solid nodes; psi_init gets the
 // pseudopotential of these populations (the reference of the FP16 form for the first step)
-template <typename S>
+template <typename S, class L>
 __global__ void k_init_f(Prm<ArT<S>> p, const double *__restrict__ rho, const cell_t *__restrict__ mask,
                          const BodyDev *__restrict__ bodies, ArT<S> *__restrict__ psi_init, S *__restrict__ fa) {
     using T = ArT<S>;
@@ -827,8 +832,8 @@ __global__ void k_init_f(Prm<ArT<S>> p, const double *__restrict__ rho, const ce
         const T ps = solid ? (T)bodies[owner_of(m)].psi_s : -expm1(-r * p.inv_rho0);
         psi_init[idx] = ps;
         const T rr = sizeof(S) == 2 ? ref_density(ps, p.rho0) : T(0);
-        sfor<19>([&](auto I) {
-            constexpr T w = Dir<decltype(I)::value>::template w<T>();
+        sfor<L::Q>([&](auto I) {
+            constexpr T w = Dir<decltype(I)::value, L>::template w<T>();
             fa[(long long)I * p.Np + idx] = pop_put<S>(w * r, w * rr);
         });
     }
@@ -839,7 +844,7 @@ __global__ void k_zero_mask(Prm<T> p, cell_t *mask) {
     for (int idx = blockIdx.x * 256 + threadIdx.x; idx < p.N; idx += gridDim.x * 256) mask[idx] = 0;
 }
 
-template <typename S, typename D>
+template <typename S, typename D, class L>
 __global__ void k_fields(Prm<ArT<S>> p, int which, const S *__restrict__ f, const cell_t *__restrict__ mask,
                          const ArT<S> *__restrict__ psi, const double *__restrict__ phi, D *__restrict__ dst) {
     using T = ArT<S>;
@@ -857,10 +862,10 @@ __global__ void k_fields(Prm<ArT<S>> p, int which, const S *__restrict__ f, cons
         } else if (!(m & C_SOLID)) {
             const T rr = sizeof(S) == 2 ? ref_density(psi[idx], p.rho0) : T(0);
             double s = 0.0;
-            sfor<19>([&](auto I) {
+            sfor<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                const double c = which == 0 ? 1.0 : (which == 1 ? Dir<i>::x : (which == 2 ? Dir<i>::y : Dir<i>::z));
-                s += c * (double)pop_get<S>(f[(long long)i * p.Np + idx], Dir<i>::template w<T>() * rr);
+                const double c = which == 0 ? 1.0 : (which == 1 ? Dir<i, L>::x : (which == 2 ? Dir<i, L>::y : Dir<i, L>::z));
+                s += c * (double)pop_get<S>(f[(long long)i * p.Np + idx], Dir<i, L>::template w<T>() * rr);
             });
             out = s;
         }

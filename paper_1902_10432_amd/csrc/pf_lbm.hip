@@ -39,6 +39,7 @@ struct pf_lbm {
     pf_lbm_config cfg;
     int nb = 0;
     int prec = PF_LBM_FP32;
+    int q = 19;  // velocities of the lattice (D3Q19 or D3Q27)
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     Layout L{};
@@ -86,7 +87,7 @@ int fail(pf_lbm *h, int code, const char *fmt, ...) {
 size_t pop_size(int prec) { return prec == PF_LBM_FP64 ? 8 : (prec == PF_LBM_FP16_STORE ? 2 : 4); }
 size_t real_size(int prec) { return prec == PF_LBM_FP64 ? 8 : 4; }
 
-Layout make_layout(long long Np, int nb, int prec, int cpart_n, int force_grid) {
+Layout make_layout(long long Np, int nb, int prec, int q, int cpart_n, int force_grid) {
     const size_t rs = real_size(prec), ps = pop_size(prec);
     Layout L{};
     size_t off = 0;
@@ -95,8 +96,8 @@ Layout make_layout(long long Np, int nb, int prec, int cpart_n, int force_grid) 
         off = align_up(off + bytes);
         return o;
     };
-    L.fA = take((size_t)19 * Np * ps);
-    L.fB = take((size_t)19 * Np * ps);
+    L.fA = take((size_t)q * Np * ps);
+    L.fB = take((size_t)q * Np * ps);
     // pseudopotential of this step and of the previous one (by step parity)
     L.psi = take((size_t)Np * rs);
     L.psiB = take((size_t)Np * rs);
@@ -268,7 +269,7 @@ void launch_phase_update(pf_lbm *h, const Prm<T> &p, int par, StepState *st, con
 }
 
 // one time step (Sec. 3): fluid, body forces + rigid update, phase fields, reclassification
-template <typename S>
+template <typename S, class Lat>
 int enqueue_step(pf_lbm *h) {
     using T = ArT<S>;
     const Prm<T> p = make_prm<T>(h);
@@ -300,17 +301,17 @@ int enqueue_step(pf_lbm *h) {
         ++h->timed;
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
-    k_psi<S><<<gd, dim3(h->psi_bs), 0, s>>>(p, fc, mask, cur, psi_prev, psi);
+    k_psi<S, Lat><<<gd, dim3(h->psi_bs), 0, s>>>(p, fc, mask, cur, psi_prev, psi);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
-    k_collide_stream<S><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + h->rows - 1) / h->rows, h->cfg.nz), dim3(64, h->rows),
-                          0, s>>>(
+    k_collide_stream<S, Lat><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + h->rows - 1) / h->rows, h->cfg.nz),
+                               dim3(64, h->rows), 0, s>>>(
         p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->cgrid);
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
         const dim3 gb(h->box_grid);
-        k_body_forces<S><<<dim3(fbk), dim3(64 * force_waves<T>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev, mask, cur,
-                                                                            pforce);
+        k_body_forces<S, Lat><<<dim3(fbk), dim3(64 * force_waves<T, Lat>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev,
+                                                                                      mask, cur, pforce);
         // one kernel per sweep; the phase fields end in buffer A every step
         k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB,
                                         (double *)(h->ws + h->L.hist), HIST_CAP);
@@ -319,8 +320,8 @@ int enqueue_step(pf_lbm *h) {
         uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
         launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
         const dim3 ge(std::min(h->box_grid, 256));
-        k_convert_gather<S><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP);
-        k_post<S><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP, 0);
+        k_convert_gather<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP);
+        k_post<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP, 0);
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[3], s));
     HIPCHK(h, hipGetLastError());
@@ -328,7 +329,7 @@ int enqueue_step(pf_lbm *h) {
     return PF_LBM_OK;
 }
 
-template <typename S>
+template <typename S, class Lat>
 int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, const double *phi0,
                 const std::vector<BodyDev> &bodies, const StepState &st0) {
     using T = ArT<S>;
@@ -366,20 +367,20 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
     S *fA = fbuf<S>(h, 0), *fB = fbuf<S>(h, 1);
     // populations at rest into fA (reads the staged density in the fB area) ...
     T *psi_init = (T *)(h->ws + h->L.psiB);  // the "previous step" of step 0
-    k_init_f<S><<<gd, b, 0, s>>>(p, tmp, mask, (const BodyDev *)(h->ws + h->L.bodies), psi_init, fA);
+    k_init_f<S, Lat><<<gd, b, 0, s>>>(p, tmp, mask, (const BodyDev *)(h->ws + h->L.bodies), psi_init, fA);
     HIPCHK(h, hipStreamSynchronize(s));
     // ... then clear fB (solid nodes keep empty populations in both buffers)
-    HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)19 * h->Np * sizeof(S), s));
+    HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)Lat::Q * h->Np * sizeof(S), s));
     // neighbour bits of the cell words
     if (h->nb > 0)
-        k_post<S><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA, psi_init, (const uint32_t *)(h->ws + h->L.evlist),
-                                                   EV_CAP, 1);
+        k_post<S, Lat><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA, psi_init,
+                                                        (const uint32_t *)(h->ws + h->L.evlist), EV_CAP, 1);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
     return PF_LBM_OK;
 }
 
-template <typename S>
+template <typename S, class Lat>
 void launch_fields(pf_lbm *h, int which, int par, void *dst, int dst_dtype) {
     using T = ArT<S>;
     const dim3 g(std::max(1, std::min(h->dense_blocks, 65535))), b(256);
@@ -390,9 +391,9 @@ void launch_fields(pf_lbm *h, int which, int par, void *dst, int dst_dtype) {
     const T *psi = (const T *)(h->ws + (par ? h->L.psi : h->L.psiB));
     const double *phi = (const double *)(h->ws + h->L.phiA);
     if (dst_dtype == PF_LBM_DST_F64)
-        k_fields<S, double><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
+        k_fields<S, double, Lat><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (double *)dst);
     else
-        k_fields<S, float><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
+        k_fields<S, float, Lat><<<g, b, 0, h->stream>>>(p, which, f, mask, psi, phi, (float *)dst);
 }
 
 }  // namespace
@@ -408,10 +409,11 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
         return fail(nullptr, PF_LBM_EINVAL, "cfg->struct_size %u < %zu", cfg->struct_size, sizeof(pf_lbm_config));
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return fail(nullptr, PF_LBM_EINVAL, "grid sizes must be >= 1");
     const long long N = (long long)cfg->nx * cfg->ny * cfg->nz;
-    if (N * 19 >= (1LL << 31) * 8LL || N >= (1LL << 31)) return fail(nullptr, PF_LBM_EINVAL, "grid too large");
+    if (N * 27 >= (1LL << 31) * 8LL || N >= (1LL << 31)) return fail(nullptr, PF_LBM_EINVAL, "grid too large");
     if (n_bodies < 0 || n_bodies > PF_LBM_MAX_BODIES)
         return fail(nullptr, PF_LBM_EINVAL, "n_bodies must be in [0, %d]", PF_LBM_MAX_BODIES);
-    if (cfg->lattice != PF_LBM_D3Q19) return fail(nullptr, PF_LBM_EUNSUPPORTED, "only the D3Q19 lattice is built");
+    if (cfg->lattice != PF_LBM_D3Q19 && cfg->lattice != PF_LBM_D3Q27)
+        return fail(nullptr, PF_LBM_EUNSUPPORTED, "lattice must be PF_LBM_D3Q19 or PF_LBM_D3Q27");
     if (cfg->precision != PF_LBM_FP64 && cfg->precision != PF_LBM_FP32 && cfg->precision != PF_LBM_FP16_STORE)
         return fail(nullptr, PF_LBM_EUNSUPPORTED, "precision must be PF_LBM_FP64, PF_LBM_FP32 or PF_LBM_FP16_STORE");
     if (!(cfg->tau > 0.5)) return fail(nullptr, PF_LBM_EINVAL, "tau must exceed 1/2");
@@ -467,7 +469,7 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
     const int box_grid = std::min(box_blocks, 2048), force_grid = std::min((box_blocks + 3) / 4, 256);
     const int cgrid = box_grid;
-    const Layout L = make_layout(Np, n_bodies, cfg->precision, std::max(cgrid, box_grid), force_grid);
+    const Layout L = make_layout(Np, n_bodies, cfg->precision, cfg->lattice, std::max(cgrid, box_grid), force_grid);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
     if (!workspace) return PF_LBM_OK;
     if (!out) return fail(nullptr, PF_LBM_EINVAL, "out is NULL");
@@ -481,6 +483,7 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     h->cfg.sigma = nullptr;
     h->nb = n_bodies;
     h->prec = cfg->precision;
+    h->q = cfg->lattice;
     h->stream = (hipStream_t)hip_stream;
     h->ws = (char *)workspace;
     h->L = L;
@@ -516,9 +519,12 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     StepState st0;
     std::memset(&st0, 0, sizeof st0);
     for (int d = 0; d < 6; ++d) st0.box[0][d] = st0.box[1][d] = box[d];
-    int rc = h->prec == PF_LBM_FP64   ? init_device<double>(h, bodies, rho0, phi0, bd, st0)
-             : h->prec == PF_LBM_FP32 ? init_device<float>(h, bodies, rho0, phi0, bd, st0)
-                                      : init_device<half_t>(h, bodies, rho0, phi0, bd, st0);
+    int rc = h->q == 27 ? (h->prec == PF_LBM_FP64   ? init_device<double, D3Q27>(h, bodies, rho0, phi0, bd, st0)
+                           : h->prec == PF_LBM_FP32 ? init_device<float, D3Q27>(h, bodies, rho0, phi0, bd, st0)
+                                                    : init_device<half_t, D3Q27>(h, bodies, rho0, phi0, bd, st0))
+                        : (h->prec == PF_LBM_FP64   ? init_device<double, D3Q19>(h, bodies, rho0, phi0, bd, st0)
+                           : h->prec == PF_LBM_FP32 ? init_device<float, D3Q19>(h, bodies, rho0, phi0, bd, st0)
+                                                    : init_device<half_t, D3Q19>(h, bodies, rho0, phi0, bd, st0));
     if (rc != PF_LBM_OK) {
         g_init_error = h->err;
         delete h;
@@ -531,9 +537,13 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
 namespace {
 
 int eager_step(pf_lbm *h) {
-    return h->prec == PF_LBM_FP64 ? enqueue_step<double>(h)
-           : h->prec == PF_LBM_FP32 ? enqueue_step<float>(h)
-                                    : enqueue_step<half_t>(h);
+    if (h->q == 27)
+        return h->prec == PF_LBM_FP64 ? enqueue_step<double, D3Q27>(h)
+               : h->prec == PF_LBM_FP32 ? enqueue_step<float, D3Q27>(h)
+                                        : enqueue_step<half_t, D3Q27>(h);
+    return h->prec == PF_LBM_FP64 ? enqueue_step<double, D3Q19>(h)
+           : h->prec == PF_LBM_FP32 ? enqueue_step<float, D3Q19>(h)
+                                    : enqueue_step<half_t, D3Q19>(h);
 }
 
 // capture an even/odd step pair on the handle's stream into an executable graph; on any failure
@@ -623,12 +633,21 @@ int pf_lbm_fields(pf_lbm *h, int32_t which, void *dst, int32_t dst_dtype) {
     const int par = (int)(h->steps & 1);
     const dim3 g(std::max(1, std::min(h->dense_blocks, 65535))), b(256);
     const cell_t *mask = (const cell_t *)(h->ws + h->L.mask);
-    if (h->prec == PF_LBM_FP64)
-        launch_fields<double>(h, which, par, dst, dst_dtype);
-    else if (h->prec == PF_LBM_FP32)
-        launch_fields<float>(h, which, par, dst, dst_dtype);
-    else
-        launch_fields<half_t>(h, which, par, dst, dst_dtype);
+    if (h->q == 27) {
+        if (h->prec == PF_LBM_FP64)
+            launch_fields<double, D3Q27>(h, which, par, dst, dst_dtype);
+        else if (h->prec == PF_LBM_FP32)
+            launch_fields<float, D3Q27>(h, which, par, dst, dst_dtype);
+        else
+            launch_fields<half_t, D3Q27>(h, which, par, dst, dst_dtype);
+    } else {
+        if (h->prec == PF_LBM_FP64)
+            launch_fields<double, D3Q19>(h, which, par, dst, dst_dtype);
+        else if (h->prec == PF_LBM_FP32)
+            launch_fields<float, D3Q19>(h, which, par, dst, dst_dtype);
+        else
+            launch_fields<half_t, D3Q19>(h, which, par, dst, dst_dtype);
+    }
     HIPCHK(h, hipGetLastError());
     return PF_LBM_OK;
 }

@@ -75,9 +75,17 @@ def test_invalid_configs_rejected(B, field, value, code):
 def test_unsupported_lattice_and_precision(B):
     w = uniform_fluid((4, 4, 4))
     cfg, sig, bodies = _cfg(B, w)
-    cfg.lattice = 27
+    cfg.lattice = 15
     rc, _, _ = B.pf_lbm_init(cfg, 0, bodies, w.rho0.reshape(-1), None, 0, 0, 0)
-    assert rc == B.PF_LBM_EUNSUPPORTED and "D3Q19" in B.pf_lbm_last_error(None)
+    assert rc == B.PF_LBM_EUNSUPPORTED and "D3Q27" in B.pf_lbm_last_error(None)
+    # D3Q27 is accepted and needs room for 27 populations per node in both copies
+    sizes = {}
+    for lat in (19, 27):
+        cfg.lattice = lat
+        rc, _, need = B.pf_lbm_init(cfg, 0, bodies, w.rho0.reshape(-1), None, 0, 0, 0)
+        assert rc == B.PF_LBM_OK
+        sizes[lat] = need
+    assert sizes[27] - sizes[19] >= 2 * 8 * 64 * 8
     cfg.lattice = 19
     cfg.precision = 7
     rc, _, _ = B.pf_lbm_init(cfg, 0, bodies, w.rho0.reshape(-1), None, 0, 0, 0)

@@ -1,0 +1,65 @@
+"""GPU parity on the D3Q27 lattice of Sec. 3.2.1 (the library against the FP64 oracle run on the
+same lattice), at the paper's relaxation time tau = 1.1 where the workload allows.
+
+Bounds as for D3Q19: FP64 at round-off (relative L2 <= 1e-11, forces <= 1e-9); FP32 relative L2
+<= 1e-5 on density and phase fields and <= 1e-4 on body forces after 200 steps (force error over
+max(|F_oracle|, pi sigma R)); FP16 population storage <= 1e-3 on body forces."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from pflbm_inputs import plates_bridge, tiny_moving_body, uniform_fluid  # noqa: E402
+from test_gpu_parity import SIGMA, _compare, _pair, _print  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_d3q27_tiny_moving_bodies_fp64(oracle_mod, torch_cuda):
+    w = tiny_moving_body(second_body=True, lattice=27, tau=1.1)
+    w.params["e0"] = 0.5
+    sim, ref = _pair(oracle_mod, w, 60, "fp64")
+    _compare(sim, ref, 1e-11, 1e-9)
+    dg, do = sim.diag(), ref.diag()
+    assert dg["n_f2s"] == do["n_f2s"] and dg["n_s2f"] == do["n_s2f"] and dg["n_f2s"] > 0
+
+
+@pytest.mark.parametrize("shape", [(7, 9, 13), (12, 1, 17)])
+def test_d3q27_ragged_and_flat_grids_fp64(oracle_mod, torch_cuda, shape):
+    from pflbm_inputs import coexistence_densities, liquid_density
+    from pflbm_inputs.geometry import grid, mimg
+    rv, rl = coexistence_densities()
+    x, y, z = grid(shape)
+    nz, ny, nx = shape
+    d = np.sqrt(mimg(x - nx / 2, nx) ** 2 + mimg(y - ny / 2, ny) ** 2 + mimg(z - nz / 2, nz) ** 2) - min(nx, 6) / 2.5
+    w = uniform_fluid(shape, G=-5.0, lattice=27, tau=1.1)
+    w.rho0 = liquid_density(d, rl, rv, 3.0)
+    sim, ref = _pair(oracle_mod, w, 30, "fp64")
+    _compare(sim, ref, 1e-11, 1e-9)
+
+
+def test_d3q27_plates_bridge_fp64_200_steps(oracle_mod, torch_cuda):
+    w = plates_bridge(lattice=27, tau=1.1)
+    sim, ref = _pair(oracle_mod, w, 200, "fp64")
+    _compare(sim, ref, 1e-11, 1e-9)
+
+
+@pytest.mark.parametrize("precision,tol_field,tol_force", [("fp32", 1e-5, 1e-4), ("fp16", 1e-3, 1e-3)])
+def test_d3q27_plates_bridge_reduced_precision(oracle_mod, torch_cuda, precision, tol_field, tol_force):
+    w = plates_bridge(lattice=27, tau=1.1)
+    sim, ref = _pair(oracle_mod, w, 200, precision)
+    _compare(sim, ref, tol_field, tol_force, force_scale=math.pi * SIGMA * 6.0)
+
+
+def test_d3q27_rest_state_and_mass(oracle_mod, torch_cuda):
+    w = uniform_fluid((6, 5, 7), rho=0.8, G=-5.0, lattice=27)
+    sim, ref = _pair(oracle_mod, w, 20, "fp32")
+    assert np.abs(sim.rho() - 0.8).max() < 1e-6
+    assert np.abs(sim.mom()).max() < 1e-7
