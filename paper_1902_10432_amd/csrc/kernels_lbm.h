@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     {
         const T rin = H ? ref_density(psi_prev[idx], p.rho0) : T(0);  // reference of the inputs
         sfor<L::Q>([&](auto I) {
-            f[I] = pop_get<S>(ldb(fin + (long long)I * Np, is), Dir<decltype(I)::value, L>::template w<T>() * rin);
+            f[I] = pop_get<S>(ldb_nt(fin + (long long)I * Np, is), Dir<decltype(I)::value, L>::template w<T>() * rin);
         });
     }
     // moments from pair sums and differences
