@@ -40,6 +40,7 @@ struct Gemm {
     long long scm, scn;
     const float *bias;
     int M, N, K, act;
+    int vec;  // k_gemm_bf16_rows: 16-byte operand loads (K, row strides multiples of 8, aligned bases)
 };
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
@@ -70,6 +71,121 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
         if (g.Cf) g.Cf[o] = z;
         if (g.Cb) g.Cb[o] = (__bf16)(g.act ? silu(z) : z);
     }
+}
+
+// The same product when A and B are contiguous along K (sak = sbk = 1) and N >= 16, with the
+// BF16 result written row-major (scn = 1).  A block of 4 waves computes 64 rows across up to
+// 16 NT columns (blockIdx.y picks the column chunk): the B columns are staged in LDS, 128 K values
+// at a time (rows padded by 16 bytes so that the 16 lanes reading one K chunk of 16 columns hit
+// distinct banks), and each wave takes a 16-row strip, loading its A fragment (one 16-byte load
+// per lane when g.vec, else element by element) and reusing it for the NT products of the strip.
+// The BF16 strip is written through LDS as 16-byte row segments.  Every wave takes part in the
+// staging, also one past the last row.
+template <int NT>
+__global__ __launch_bounds__(256) void k_gemm_bf16_rows(Gemm g) {
+    constexpr int KC = 128, LD = KC + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 wl[16 * NT][LD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tm = blockIdx.x * 4 + wave;
+    const int n0 = blockIdx.y * 16 * NT;
+    const int row = tm * 16 + (lane & 15), kq = 8 * (lane >> 4);
+    const bool active = tm * 16 < g.M;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int kc = 0; kc < g.K; kc += KC) {
+        for (int e = tid * 8; e < 16 * NT * KC; e += 256 * 8) {
+            const int r = e / KC, c = e - r * KC;
+            bf16x8 v = zero;
+            if (n0 + r < g.N) {
+                const __bf16 *src = g.B + (long long)(n0 + r) * g.sbn + kc + c;
+                if (g.vec) {
+                    if (kc + c < g.K) v = *(const bf16x8 *)src;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (kc + c + j < g.K) v[j] = src[j];
+                }
+            }
+            *(bf16x8 *)&wl[r][c] = v;
+        }
+        __syncthreads();
+        if (active) {
+            for (int k0 = 0; k0 < KC && kc + k0 < g.K; k0 += 32) {
+                const int k = kc + k0 + kq;
+                bf16x8 a = zero;
+                if (row < g.M) {
+                    const __bf16 *src = g.A + row * g.sam + k;
+                    if (g.vec) {
+                        if (k < g.K) a = *(const bf16x8 *)src;
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (k + j < g.K) a[j] = src[j];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (n0 + 16 * t >= g.N) break;  // uniform
+                    const bf16x8 b = *(const bf16x8 *)&wl[16 * t + (lane & 15)][k0 + kq];
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: z = acc + bias; FP32 z element by element; the BF16 strip (16 x 16 NT) goes to
+    // this wave's part of the (now free) staging area, then out as 16-byte row segments
+    __bf16 *strip = &wl[0][0] + wave * (16 * 16 * NT);
+    const int ncols = min(16 * NT, g.N - n0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (16 * t >= ncols) break;
+        const int nl = 16 * t + (lane & 15), n = n0 + nl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ml = 4 * (lane >> 4) + r, m = tm * 16 + ml;
+            const float z = acc[t][r] + (g.bias && n < g.N ? g.bias[n] : 0.0f);
+            if (active && g.Cf && m < g.M && n < g.N) g.Cf[m * g.scm + n] = z;
+            strip[ml * (16 * NT) + nl] = (__bf16)(g.act ? silu(z) : z);
+        }
+    }
+    __syncthreads();
+    if (!active || !g.Cb) return;
+    // 16 rows x ncols columns, ncols a multiple of 16: 8-element segments
+    const int segs = ncols / 8;
+    for (int q = lane; q < 16 * segs; q += 64) {
+        const int ml = q / segs, c = (q - ml * segs) * 8, m = tm * 16 + ml;
+        if (m >= g.M) continue;
+        __bf16 *dst = g.Cb + m * g.scm + n0 + c;
+        const bf16x8 v = *(const bf16x8 *)&strip[ml * (16 * NT) + c];
+        if (g.vec)
+            *(bf16x8 *)dst = v;
+        else
+            for (int j = 0; j < 8; ++j) dst[j] = v[j];
+    }
+}
+
+// Output layer with one output: y = A w + b over K (a multiple of 8) BF16 inputs, 16 lanes per
+// row (each takes 8 consecutive inputs per 128), summed across the 16 lanes in a fixed order.
+__global__ __launch_bounds__(256) void k_last_layer(const __bf16 *__restrict__ A, int M, int K,
+                                                    const __bf16 *__restrict__ w, const float *__restrict__ bias,
+                                                    float *__restrict__ y) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int row = (int)(t >> 4), sub = (int)(t & 15);
+    float acc = 0.0f;
+    if (row < M) {
+        for (int k = 8 * sub; k < K; k += 128) {
+            const bf16x8 a = *(const bf16x8 *)(A + (long long)row * K + k);
+            const bf16x8 b = *(const bf16x8 *)(w + k);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc = fmaf((float)a[j], (float)b[j], acc);
+        }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (row < M && sub == 0) y[row] = acc + bias[0];
 }
 
 // BF16 copy of an FP32 array
@@ -197,24 +313,42 @@ X *at(pf_mlp *h, size_t off) {
 
 void gemm(pf_mlp *h, const __bf16 *A, long long sam, long long sak, const __bf16 *B, long long sbk, long long sbn,
           float *Cf, __bf16 *Cb, long long scm, long long scn, const float *bias, int M, int N, int K, int act) {
-    Gemm g{A, sam, sak, B, sbk, sbn, Cf, Cb, scm, scn, bias, M, N, K, act};
+    Gemm g{A, sam, sak, B, sbk, sbn, Cf, Cb, scm, scn, bias, M, N, K, act, 0};
+    g.vec = K % 8 == 0 && sam % 8 == 0 && sbn % 8 == 0 && scm % 8 == 0 && ((uintptr_t)A % 16) == 0 &&
+            ((uintptr_t)B % 16) == 0 && ((uintptr_t)Cb % 16) == 0;
+    const bool rows = sak == 1 && sbk == 1 && scn == 1 && N >= 16 && N % 16 == 0;
+    if (rows) {
+        constexpr int NT = 8;
+        const dim3 grid((unsigned)(((M + 15) / 16 + 3) / 4), (unsigned)((N + 16 * NT - 1) / (16 * NT)));
+        k_gemm_bf16_rows<NT><<<grid, 256, 0, h->stream>>>(g);
+        return;
+    }
     const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
     k_gemm_bf16<<<(tiles + 3) / 4, 256, 0, h->stream>>>(g);
 }
 
 int grid_for(long long n) { return (int)std::max(1LL, std::min(4096LL, (n + 255) / 256)); }
 
-// forward pass of n samples; leaves Z_l, A_l and the output in the workspace
-int run_forward(pf_mlp *h, const float *x, int n) {
+// forward pass of n samples; leaves A_l (and with keep_z the FP32 pre-activations Z_l, which only
+// the backward pass needs) and the output in the workspace
+int run_forward(pf_mlp *h, const float *x, int n, bool keep_z, float *y_out = nullptr) {
     const LayerMap &lm = h->lm;
-    k_to_bf16<<<grid_for((long long)n * h->cfg.n_in), 256, 0, h->stream>>>(x, at<__bf16>(h, h->Xb), n * h->cfg.n_in);
+    const int nin = h->cfg.n_in;
+    k_to_bf16<<<grid_for((long long)n * nin), 256, 0, h->stream>>>(x, at<__bf16>(h, h->Xb), n * nin);
     for (int l = 0; l < lm.n; ++l) {
         const int I = lm.in[l], O = lm.out[l];
         const __bf16 *Ain = l == 0 ? at<__bf16>(h, h->Xb) : at<__bf16>(h, h->A[l - 1]);
         const bool last = l == lm.n - 1;
-        // Z = A_in W^T + b: B[k][n] = W[n][k]
-        gemm(h, Ain, I, 1, at<__bf16>(h, h->Wb) + lm.wb[l], 1, I, last ? at<float>(h, h->Y) : at<float>(h, h->Z[l]),
-             last ? nullptr : at<__bf16>(h, h->A[l]), O, 1, at<float>(h, h->P) + lm.b[l], n, O, I, last ? 0 : 1);
+        const __bf16 *Wl = at<__bf16>(h, h->Wb) + lm.wb[l];
+        const float *bl = at<float>(h, h->P) + lm.b[l];
+        float *Zl = last ? (y_out ? y_out : at<float>(h, h->Y)) : (keep_z ? at<float>(h, h->Z[l]) : nullptr);
+        if (last && O == 1 && I % 8 == 0) {
+            const long long th = (long long)n * 16;
+            k_last_layer<<<(unsigned)((th + 255) / 256), 256, 0, h->stream>>>(Ain, n, I, Wl, bl, Zl);
+        } else {
+            // Z = A_in W^T + b: B[k][n] = W[n][k]
+            gemm(h, Ain, I, 1, Wl, 1, I, Zl, last ? nullptr : at<__bf16>(h, h->A[l]), O, 1, bl, n, O, I, last ? 0 : 1);
+        }
     }
     MCHK(h, hipGetLastError());
     return PF_LBM_OK;
@@ -250,7 +384,7 @@ int run_backward(pf_mlp *h, int n) {
 }
 
 int loss_and_grad(pf_mlp *h, const float *x, const float *t, int n) {
-    int rc = run_forward(h, x, n);
+    int rc = run_forward(h, x, n, true);
     if (rc != PF_LBM_OK) return rc;
     k_loss<<<1, 256, 0, h->stream>>>(at<float>(h, h->Y), t, n, at<float>(h, h->dY), at<__bf16>(h, h->dYb),
                                      at<double>(h, h->loss));
@@ -385,10 +519,7 @@ int pf_mlp_get_params(pf_mlp *h, float *params) {
 int pf_mlp_forward(pf_mlp *h, const float *x, int32_t n, float *y) {
     if (!h || !x || !y) return mfail(h, PF_LBM_EINVAL, "NULL argument");
     if (n < 1 || n > h->cfg.max_batch) return mfail(h, PF_LBM_EINVAL, "n must be in [1, max_batch]");
-    const int rc = run_forward(h, x, n);
-    if (rc != PF_LBM_OK) return rc;
-    MCHK(h, hipMemcpyAsync(y, h->ws + h->Y, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
-    return PF_LBM_OK;
+    return run_forward(h, x, n, false, y);
 }
 
 int pf_mlp_gradients(pf_mlp *h, const float *x, const float *t, int32_t n, float *grad, double *loss) {
