@@ -213,6 +213,99 @@ __global__ void k_refresh_weights(LayerMap lm, const float *__restrict__ p, __bf
     }
 }
 
+// Whole forward pass for hidden width 128 and up to 32 inputs (inference): a block of 4 waves
+// carries 64 rows through every layer.  Each wave keeps its 16-row activation strip in LDS (BF16,
+// rows padded by 16 bytes), the block stages one layer's weights at a time in LDS, and every
+// hidden product runs on v_mfma_f32_16x16x32_bf16 with the A fragment read from the strip; the
+// first layer takes the FP32 inputs rounded to BF16 (K padded with zeros to 32) and the output
+// layer is a dot product of each strip row with the output weights (4 lanes per row, fixed
+// order).  Only the inputs and outputs cross HBM.  The arithmetic of each product is that of the
+// layer-by-layer path; the output sum runs in another fixed order.
+__global__ __launch_bounds__(256) void k_mlp_forward_fused(const float *__restrict__ x, int M, int nin, LayerMap lm,
+                                                           const __bf16 *__restrict__ Wb, const float *__restrict__ P,
+                                                           float *__restrict__ y) {
+    constexpr int H = 128, LD = H + 8, NT = H / 16;
+    __shared__ __attribute__((aligned(16))) __bf16 wl[H][LD];
+    __shared__ __attribute__((aligned(16))) __bf16 act[4][16][LD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tm = blockIdx.x * 4 + wave;
+    const int rowl = lane & 15, kq = 8 * (lane >> 4);
+    const int row = tm * 16 + rowl;
+    const bool active = tm * 16 < M;
+    const bf16x8 zero = {};
+    f32x4 acc[NT];
+    // ---- layer 0 (K = nin <= 32, one product step)
+    {
+        const __bf16 *W = Wb + lm.wb[0];
+        for (int e = tid; e < H * 32; e += 256) {
+            const int r = e >> 5, c = e & 31;
+            wl[r][c] = c < nin ? W[r * nin + c] : (__bf16)0.0f;
+        }
+        __syncthreads();
+        bf16x8 a = zero;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (active && row < M && kq + j < nin) a[j] = (__bf16)x[(long long)row * nin + kq + j];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8 b = *(const bf16x8 *)&wl[16 * t + rowl][kq];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+        const float *bias = P + lm.b[0];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                act[wave][4 * (lane >> 4) + r][16 * t + rowl] = (__bf16)silu(acc[t][r] + bias[16 * t + rowl]);
+        __syncthreads();
+    }
+    // ---- hidden layers
+    for (int l = 1; l < lm.n - 1; ++l) {
+        const __bf16 *W = Wb + lm.wb[l];
+        for (int e = tid * 8; e < H * H; e += 256 * 8) {
+            const int r = e / H, c = e - r * H;
+            *(bf16x8 *)&wl[r][c] = *(const bf16x8 *)(W + e);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < H; k0 += 32) {
+            const bf16x8 a = *(const bf16x8 *)&act[wave][rowl][k0 + kq];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x8 b = *(const bf16x8 *)&wl[16 * t + rowl][k0 + kq];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave is done with the staged weights and its strip
+        const float *bias = P + lm.b[l];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                act[wave][4 * (lane >> 4) + r][16 * t + rowl] = (__bf16)silu(acc[t][r] + bias[16 * t + rowl]);
+        __syncthreads();
+    }
+    // ---- output layer: row 4 lanes x 32 inputs
+    const int L = lm.n - 1;
+    const __bf16 *w = Wb + lm.wb[L];
+    const int rr = lane >> 2, part = lane & 3;
+    float s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = 32 * part + 8 * q;
+        const bf16x8 a = *(const bf16x8 *)&act[wave][rr][k];
+        const bf16x8 b = *(const bf16x8 *)(w + k);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s = fmaf((float)a[j], (float)b[j], s);
+    }
+    s += __shfl_xor(s, 1, 4);
+    s += __shfl_xor(s, 2, 4);
+    const int m = tm * 16 + rr;
+    if (active && part == 0 && m < M) y[m] = s + P[lm.b[L]];
+}
+
 // dZ = dA * silu'(Z) (FP32 and BF16)
 __global__ void k_silu_back(const float *__restrict__ dA, const float *__restrict__ Z, float *__restrict__ dZ,
                             __bf16 *__restrict__ dZb, int n) {
@@ -519,6 +612,12 @@ int pf_mlp_get_params(pf_mlp *h, float *params) {
 int pf_mlp_forward(pf_mlp *h, const float *x, int32_t n, float *y) {
     if (!h || !x || !y) return mfail(h, PF_LBM_EINVAL, "NULL argument");
     if (n < 1 || n > h->cfg.max_batch) return mfail(h, PF_LBM_EINVAL, "n must be in [1, max_batch]");
+    if (h->cfg.hidden == 128 && h->cfg.n_in <= 32) {
+        k_mlp_forward_fused<<<(unsigned)((n + 63) / 64), 256, 0, h->stream>>>(x, n, h->cfg.n_in, h->lm,
+                                                                            at<__bf16>(h, h->Wb), at<float>(h, h->P), y);
+        MCHK(h, hipGetLastError());
+        return PF_LBM_OK;
+    }
     return run_forward(h, x, n, false, y);
 }
 

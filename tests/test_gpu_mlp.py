@@ -119,3 +119,18 @@ def test_training_reduces_loss(torch_cuda):
     assert last < 0.02 * first
     y = net.forward(xd).cpu().numpy()
     assert _rel(y, t) < 0.15
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000, 4097])
+def test_fused_inference_matches_layered_forward(torch_cuda, n):
+    """Inference at width 128 runs the whole network in one kernel; the loss the gradient call
+    reports (its layer-by-layer forward) against the fused outputs as targets is the mean squared
+    difference of the two forward passes: identical products, output sums in another order."""
+    torch = torch_cuda
+    net, _, x, _ = _setup(torch, 4, 128, 4, n, seed=41 + n)
+    xd = torch.from_numpy(x).cuda()
+    y = net.forward(xd)
+    loss, _ = net.gradients(xd, y)
+    rms = float(torch.sqrt((y ** 2).mean()))
+    _print(f"  n={n}: rms diff {loss ** 0.5:.2e} of rms {rms:.2e}")
+    assert loss ** 0.5 <= 1e-5 * rms
