@@ -319,7 +319,8 @@ int enqueue_step(pf_lbm *h) {
         k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB, nullptr, 0);
         uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
         launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
-        const dim3 ge(std::min(h->box_grid, 256));
+        // conversion passes: usually return at once (no node changed side), so a small grid
+        const dim3 ge(std::min(h->box_grid, 64));
         k_convert_gather<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP);
         k_post<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP, 0);
     }
@@ -467,7 +468,10 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     // box kernels: about one thread per cell of the initial box with room to grow (grid-stride
     // loops cover larger boxes), at most 4096 blocks
     const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
-    const int box_grid = std::min(box_blocks, 2048), force_grid = std::min((box_blocks + 3) / 4, 256);
+    // box kernels: grid-stride over the box with at most two blocks per CU of the 256 (measured:
+    // 512 blocks beat 1024, 2048 and 256 on the 128^3 workload, the launch and drain of more
+    // blocks costing more than their extra parallelism gains)
+    const int box_grid = std::min(box_blocks, 512), force_grid = std::min((box_blocks + 3) / 4, 256);
     const int cgrid = box_grid;
     const Layout L = make_layout(Np, n_bodies, cfg->precision, cfg->lattice, std::max(cgrid, box_grid), force_grid);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
