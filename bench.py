@@ -227,6 +227,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=None, help="grid size override (cubic)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"])
     ap.add_argument("--lattice", type=int, default=19, choices=[19, 27], help="velocity set (27: Sec. 3.2.1)")
+    ap.add_argument("--tau", type=float, default=None, help="BGK relaxation time (workload default 1.0)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16-storage comparison")
@@ -260,6 +261,8 @@ def main() -> int:
     kw = {"n": args.n} if args.n else {}
     if args.lattice != 19:
         kw["lattice"] = args.lattice
+    if args.tau is not None:
+        kw["tau"] = args.tau
     w = make_workload(args.workload, **kw)
     q = args.lattice
     pop, arith = FORMS[args.precision]
