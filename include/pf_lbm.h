@@ -44,7 +44,7 @@ enum {
     PF_LBM_OK = 0,
     PF_LBM_EINVAL = -1,       /* invalid argument or configuration                          */
     PF_LBM_ENOMEM = -2,       /* workspace smaller than required, or a host allocation failed */
-    PF_LBM_EUNSUPPORTED = -3, /* valid for the method, not supported by this build          */
+    PF_LBM_EUNSUPPORTED = -3, /* valid for the method, not supported by this library        */
     PF_LBM_EDEVICE = -4,      /* a HIP runtime call failed                                  */
     PF_LBM_ENONFINITE = -5,   /* non-finite body force or state, or advection CFL above 1   */
 };
