@@ -198,13 +198,16 @@ def surrogate_run(args) -> int:
     t_data = time.perf_counter() - t0
     norm = Dp.normalisation(X, y)
     net, rep = Dp.train(X, y, norm, log=log)
-    s = Dp.deploy(net, norm, steps=args.surrogate_steps, log=log)
+    s = Dp.deploy(net, norm, steps=args.surrogate_steps, train_data=(X, y), refine_steps=args.surrogate_refine,
+                  log=log)
     fwd = mlp_forward_rate()
     rounds = s.pop("rounds")
     out = {"metric": "surrogate bridge force: GPU time per bridge, PF-LBM re-solve / network",
            "value": round(s["speedup_per_bridge"], 1), "unit": "x", "higher_is_better": True,
            "judged_rmse": round(s["rmse"], 5), "judged_field_rms": round(s["rms_field"], 5),
            "judged_rel_rmse": round(s["rmse"] / s["rms_field"], 4), "judged": s["judged"], "fallbacks": s["fallbacks"],
+           "judged_rel_rmse_first_half": round(s["rel_rmse_first_half"], 4),
+           "judged_rel_rmse_second_half": round(s["rel_rmse_second_half"], 4), "refine_steps": s["refine_steps"],
            "seconds_per_bridge_network": s["seconds_per_bridge_network"],
            "seconds_per_bridge_field": s["seconds_per_bridge_field"],
            "training": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in rep.items()},
@@ -240,6 +243,8 @@ def main() -> int:
                     help="only the bridge-force surrogate: sweep, GPU training, 1000-sphere run with re-solves")
     ap.add_argument("--surrogate-seeds", type=int, default=4, help="64-bridge sweeps of training data")
     ap.add_argument("--surrogate-steps", type=int, default=1000, help="rigid-body steps (judged every 100)")
+    ap.add_argument("--surrogate-refine", type=int, default=100,
+                    help="Adam steps on sweep + judged bridges after each judgement (0: none)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 5)

@@ -145,13 +145,15 @@ def deploy(net: Surrogate, norm, n: int = 1000, radius_unit: float = 15.0, liqui
            theta_deg: float = 30.0, steps: int = 1000, judge_every: int = 100, judge_pairs: int = 32,
            judge_box: int = 96, judge_steps: int = 2000, judge_window: int = 1000, dt: float = 5.0,
            density: float = SPHERE_DENSITY, k_n: float = 5.0, gamma_n: float = 270.0, fallback_tol: float = 0.25,
-           seed: int = 0, log=print):
+           seed: int = 0, train_data=None, refine_steps: int = 0, refine_lr: float = 2e-4, log=print):
     """Rigid-body run of n spheres (radii U[0.8, 1.2] radius_unit, seeded random packing) with
     network bridge forces.  Every judge_every steps, judge_pairs bridges (seeded choice among
     those whose pair fits the judge box) are re-solved by the field method; their errors are
     recorded, and bridges whose network force is off by more than fallback_tol of
     max(|F_field|, RMS of the judged field forces) take the field force (override) until the next
-    judgement."""
+    judgement.  With train_data = (X, y) and refine_steps > 0 the judged bridges also join the
+    training set and the network takes refine_steps Adam steps on the whole set after each
+    judgement, so each judgement measures the error on bridges the network has not seen."""
     x0, radii, L = random_packing(n, 0.8 * radius_unit, 1.2 * radius_unit, seed=seed)
     theta = math.radians(theta_deg)
     cfg = dem_config(n, L, dt, density, k_n, gamma_n, theta, liquid_fraction, GAP_MIN, GAP_MAX, norm,
@@ -160,6 +162,9 @@ def deploy(net: Surrogate, norm, n: int = 1000, radius_unit: float = 15.0, liqui
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     rounds = []
     t_steps = 0.0
+    refine = train_data is not None and refine_steps > 0
+    if refine:
+        Xr, yr = np.asarray(train_data[0], dtype=np.float64), np.asarray(train_data[1], dtype=np.float64)
     for s0 in range(0, steps, judge_every):
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -186,12 +191,27 @@ def deploy(net: Surrogate, norm, n: int = 1000, radius_unit: float = 15.0, liqui
         scale = max(float(np.sqrt(np.mean(Fp ** 2))), 1e-12)
         bad = np.abs(d) > fallback_tol * np.maximum(np.abs(Fp), scale)
         run.set_overrides(ij[pick][bad], Fp[bad])
+        t_refine = 0.0
+        if refine:
+            # the judged bridges join the training set (F / R*), then a short refinement
+            rs = 2.0 * radii[ij[pick, 0]] * radii[ij[pick, 1]] / (radii[ij[pick, 0]] + radii[ij[pick, 1]])
+            Xr = np.concatenate([Xr, feat[pick]])
+            yr = np.concatenate([yr, Fp / rs])
+            dev = net.device
+            xt = torch.from_numpy(_inputs(Xr, norm)).to(dev)
+            yt = torch.from_numpy(((yr - norm["out_shift"]) / norm["out_scale"]).astype(np.float32)).to(dev)
+            t = time.perf_counter()
+            for _ in range(refine_steps):
+                net.train_step(xt, yt, refine_lr)
+            torch.cuda.synchronize()
+            t_refine = time.perf_counter() - t
         x = run.state()["x"]
         rec = {"step": s0 + judge_every, "bridges": int(len(ij)), "judged": int(len(pick)),
                "rmse": float(np.sqrt(np.mean(d ** 2))), "rms_field": scale, "mae": float(np.abs(d).mean()),
                "fallbacks": int(bad.sum()), "surrogate_eval_s": t_eval, "field_solve_s": st["solve_s"],
                "field_setup_s": st["setup_s"], "field_mlups": st["cell_updates"] / st["solve_s"] / 1e6,
-               "mean_coordination": 2.0 * len(ij) / n, "x_finite": bool(np.isfinite(x).all())}
+               "mean_coordination": 2.0 * len(ij) / n, "x_finite": bool(np.isfinite(x).all()),
+               "refine_s": t_refine}
         rounds.append(rec)
         log(f"step {rec['step']}: {rec['bridges']} bridges, judged {rec['judged']}: RMSE {rec['rmse']:.3e} "
             f"(field RMS {scale:.3e}), {rec['fallbacks']} fallbacks; network {t_eval * 1e3:.2f} ms for all "
@@ -199,7 +219,12 @@ def deploy(net: Surrogate, norm, n: int = 1000, radius_unit: float = 15.0, liqui
     judged = [r for r in rounds if r.get("judged")]
     per_pair_net = float(np.mean([r["surrogate_eval_s"] / r["bridges"] for r in judged]))
     per_pair_field = float(np.mean([r["field_solve_s"] / r["judged"] for r in judged]))
+    half = len(judged) // 2
+    rel = [r["rmse"] / r["rms_field"] for r in judged]
     summary = {"spheres": n, "box": L, "radius_unit": radius_unit, "liquid_fraction": liquid_fraction,
+               "refine_steps": refine_steps if refine else 0,
+               "rel_rmse_first_half": float(np.mean(rel[:half])) if half else float("nan"),
+               "rel_rmse_second_half": float(np.mean(rel[half:])) if judged else float("nan"),
                "theta_deg": theta_deg, "steps": steps, "dt": dt, "step_seconds": t_steps,
                "rmse": float(np.sqrt(np.mean([r["rmse"] ** 2 for r in judged]))),
                "rms_field": float(np.sqrt(np.mean([r["rms_field"] ** 2 for r in judged]))),
