@@ -63,3 +63,29 @@ def test_d3q27_rest_state_and_mass(oracle_mod, torch_cuda):
     sim, ref = _pair(oracle_mod, w, 20, "fp32")
     assert np.abs(sim.rho() - 0.8).max() < 1e-6
     assert np.abs(sim.mom()).max() < 1e-7
+
+
+def test_d3q27_fp16_moving_bodies_with_conversion(oracle_mod, torch_cuda):
+    """FP16 population storage on D3Q27 through moving walls and node conversions (60 steps):
+    body force within 1e-3 of max(|F|, pi sigma R), same conversion counts as the oracle."""
+    w = tiny_moving_body(second_body=True, lattice=27, tau=1.1)
+    w.params["e0"] = 0.5
+    sim, ref = _pair(oracle_mod, w, 60, "fp16")
+    out = _compare(sim, ref, 2e-3, 1e-3, force_scale=math.pi * SIGMA * 2.0)
+    assert out["F"] < 1e-3
+    assert sim.diag()["n_f2s"] == ref.diag()["n_f2s"] > 0
+
+
+def test_d3q27_batch_matches_individual_runs(torch_cuda):
+    from paper_1902_10432_amd.simulation import Simulation, step_batch
+    from pflbm_inputs import bridge_pair
+    args = [((24, 28, 40), 5.0, 6.5, 3.0, 0.05, 30.0), ((20, 26, 36), 4.5, 5.0, 2.5, 0.10, 10.0)]
+    ws = [bridge_pair(*a, lattice=27) for a in args]
+    alone = [Simulation(w.params, w.bodies, w.rho0, w.phi0, precision="fp32") for w in ws]
+    for s in alone:
+        s.step(21)
+    together = [Simulation(w.params, w.bodies, w.rho0, w.phi0, precision="fp32") for w in ws]
+    step_batch(together, 21)
+    for a, b in zip(alone, together):
+        assert np.array_equal(a.rho(), b.rho()) and np.array_equal(a.phi(), b.phi())
+        assert np.array_equal(a.bodies()["F"], b.bodies()["F"])
