@@ -99,6 +99,7 @@ struct StepState {
     uint32_t step_no, pad;        // steps started (counted by the step-state publish)
     unsigned long long n_f2s, n_s2f, n_lost;
     float srad[PF_LBM_MAX_BODIES];  // largest distance of a solid node from its body's centre
+    double rep_mag[16];             // repulsion magnitude by squared node distance (r_c <= 4)
 };
 
 // per-block results of the reclassification kernel, combined at the start of the next step

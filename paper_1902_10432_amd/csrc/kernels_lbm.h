@@ -310,13 +310,8 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
     __shared__ double acc[W][PF_LBM_MAX_BODIES][6];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nbod = p.nb;
-    __shared__ double mag_tab[49];  // repulsion magnitude by squared distance (|d| <= 4 per axis)
-    for (int k = tid; k < W * PF_LBM_MAX_BODIES * 6; k += NT) (&acc[0][0][0])[k] = 0.0;
-    if (tid < 49) {
-        const double r = sqrt((double)tid);
-        mag_tab[tid] = tid > 0 && r < p.r_c ? p.e0 * (p.n_exp / p.r_c) * pow(fabs((r - p.r_c) / p.r_c), p.n_exp - 1.0) : 0.0;
-    }
-    __syncthreads();
+    // each wave clears and fills only its own row of the sums: no barrier before the scan
+    for (int k = lane; k < PF_LBM_MAX_BODIES * 6; k += 64) (&acc[wave][0][0])[k] = 0.0;
     const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
@@ -344,22 +339,37 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
             const cell_t w0 = mask[idx];
             if (!(w0 & C_SOLID)) {
                 fluid = true;
+                uint32_t mo[L::Q];  // words of the neighbours
+                const NbrU ne(x, y, z, nx, ny, nz, 1);
                 if constexpr (L::kBits) {
                     nbits = w0 & C_NBMASK;
                 } else {
-                    const NbrU nm(x, y, z, nx, ny, nz, (int)sizeof(cell_t));
-                    const uint32_t im = (uint32_t)idx * (uint32_t)sizeof(cell_t);
                     sfor<L::Q>([&](auto I) {
                         constexpr int i = decltype(I)::value;
-                        if constexpr (i > 0)
-                            if (ldb(mask, nm.template at<i>(im)) & C_SOLID) nbits |= 1u << i;
+                        if constexpr (i > 0) {
+                            mo[i] = ldb(mask, ne.template at<i>((uint32_t)idx) * 4u);
+                            if (mo[i] & C_SOLID) nbits |= 1u << i;
+                        }
                     });
                 }
                 if (nbits) {
-                    // one round of independent gathers (byte offsets from uniform bases)
-                    const NbrU ne(x, y, z, nx, ny, nz, 1);
+                    // Every gather of the node is issued in one round and unconditionally (the
+                    // neighbour values are cache-served), so the per-link selects below wait for
+                    // memory once; loads inside the per-link branches were serialised, one
+                    // memory latency per link.
                     const uint32_t ib = (uint32_t)idx * (uint32_t)sizeof(T);
                     const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
+                    S fo[L::Q];  // reflected populations f_opp(i) written by k_collide_stream
+                    T pn[L::Q];  // neighbour pseudopotentials
+                    sfor<L::Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        if constexpr (i > 0) {
+                            const uint32_t n = ne.template at<i>((uint32_t)idx);
+                            if constexpr (L::kBits) mo[i] = ldb(mask, n * 4u);
+                            fo[i] = ldb(fpost + (long long)Dir<i, L>::opp * Np, is);
+                            pn[i] = ldb(psi, n * (uint32_t)sizeof(T));
+                        }
+                    });
                     rho = sizeof(S) == 2 ? ref_density(psi_prev[idx], p.rho0) : T(0);
                     sfor<L::Q>([&](auto I) { rho += (T)ldb(fin + (long long)I * Np, is); });
                     ps0 = ldb(psi, ib);
@@ -370,13 +380,11 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                         a[i] = T(0);
                         if constexpr (i > 0) {
                             if (nbits & (1u << i)) {
-                                const uint32_t n = ne.template at<i>((uint32_t)idx);
-                                const uint32_t o = (uint32_t)owner_of(ldb(mask, n * 4u));
+                                const uint32_t o = (uint32_t)owner_of(mo[i]);
                                 own[i >> 3] |= o << (4 * (i & 7));
                                 touched |= 1u << o;
-                                a[i] = T(2) * pop_get<S>(ldb(fpost + (long long)Dir<i, L>::opp * Np, is),
-                                                         Dir<i, L>::template w<T>() * rown) +
-                                       gp * Dir<i, L>::template w<T>() * ldb(psi, n * (uint32_t)sizeof(T));
+                                a[i] = T(2) * pop_get<S>(fo[i], Dir<i, L>::template w<T>() * rown) +
+                                       gp * Dir<i, L>::template w<T>() * pn[i];
                             }
                         }
                     });
@@ -408,31 +416,43 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
             wt &= wt - 1;
             double v[6] = {0, 0, 0, 0, 0, 0};
             if ((touched & (1u << b)) && fluid) {
+                // The link midpoint is x + c_i/2, so with r the node's offset from the centre:
+                // c_i . u_w(x + c_i/2) = c_i . u_w(x) (the term c_i . (W x c_i)/2 vanishes) and
+                // (r + c_i/2) x s c_i = r x s c_i.  The wall term needs the node's rigid velocity
+                // only, and the torque is r x (sum of the link forces).
                 const BodyDev &B = bodies[b];
+                const double rx = mimg_r(x - B.X[0], nx, p.inv_n[0]), ry = mimg_r(y - B.X[1], ny, p.inv_n[1]),
+                             rz = mimg_r(z - B.X[2], nz, p.inv_n[2]);
+                const double u0x = B.V[0] + (B.W[1] * rz - B.W[2] * ry), u0y = B.V[1] + (B.W[2] * rx - B.W[0] * rz),
+                             u0z = B.V[2] + (B.W[0] * ry - B.W[1] * rx);
+                double fx = 0.0, fy = 0.0, fz = 0.0;
                 sfor<L::Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     if constexpr (i > 0) {
                         if ((nbits & (1u << i)) && ((own[i >> 3] >> (4 * (i & 7))) & 15u) == (uint32_t)b) {
-                            const double px = x + 0.5 * Dir<i, L>::x, py = y + 0.5 * Dir<i, L>::y, pz = z + 0.5 * Dir<i, L>::z;
-                            double uwx, uwy, uwz;
-                            wall_velocity(p, B, px, py, pz, uwx, uwy, uwz);
-                            const double cuw = Dir<i, L>::x * uwx + Dir<i, L>::y * uwy + Dir<i, L>::z * uwz;
+                            double cuw = 0.0;
+                            if constexpr (Dir<i, L>::x != 0) cuw += Dir<i, L>::x * u0x;
+                            if constexpr (Dir<i, L>::y != 0) cuw += Dir<i, L>::y * u0y;
+                            if constexpr (Dir<i, L>::z != 0) cuw += Dir<i, L>::z * u0z;
                             // moving-wall term g; the link carries 2 f*_i + g = 2 f_opp(i) - g to the
                             // body plus the pseudopotential reaction, both along c_i
                             const T g = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
                             const double s = (double)(a[i] - g);
-                            const double fx = s * Dir<i, L>::x, fy = s * Dir<i, L>::y, fz = s * Dir<i, L>::z;
-                            const double rx = mimg_r(px - B.X[0], nx, p.inv_n[0]), ry = mimg_r(py - B.X[1], ny, p.inv_n[1]),
-                                         rz = mimg_r(pz - B.X[2], nz, p.inv_n[2]);
-                            v[0] += fx;
-                            v[1] += fy;
-                            v[2] += fz;
-                            v[3] += ry * fz - rz * fy;
-                            v[4] += rz * fx - rx * fz;
-                            v[5] += rx * fy - ry * fx;
+                            if constexpr (Dir<i, L>::x == 1) fx += s;
+                            if constexpr (Dir<i, L>::x == -1) fx -= s;
+                            if constexpr (Dir<i, L>::y == 1) fy += s;
+                            if constexpr (Dir<i, L>::y == -1) fy -= s;
+                            if constexpr (Dir<i, L>::z == 1) fz += s;
+                            if constexpr (Dir<i, L>::z == -1) fz -= s;
                         }
                     }
                 });
+                v[0] = fx;
+                v[1] = fy;
+                v[2] = fz;
+                v[3] = ry * fz - rz * fy;
+                v[4] = rz * fx - rx * fz;
+                v[5] = rx * fy - ry * fx;
             } else if (touched & (1u << b)) {
                 for (int dz = -R; dz <= R; ++dz)
                     for (int dy = -R; dy <= R; ++dy)
@@ -444,7 +464,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                             const int b2 = owner_of(mq);
                             if (b2 <= b1 || (b != b1 && b != b2)) continue;
                             const double r = sqrt((double)d2);
-                            const double mag = mag_tab[d2];
+                            const double mag = st->rep_mag[d2];
                             // force on b1 at p, directed from q to p
                             double fx = -dx / r * mag, fy = -dy / r * mag, fz = -dz / r * mag;
                             double ax = x, ay = y, az = z;

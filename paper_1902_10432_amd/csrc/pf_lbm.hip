@@ -58,7 +58,9 @@ struct pf_lbm {
     int timed = 0;
     std::vector<hipEvent_t> ev;  // 4 per timed step: step start, kernel start, kernel end, step end
     // two steps (even, odd parity) captured once and replayed
-    hipGraphExec_t graph = nullptr;
+    // captured step sequences of GRAPH_STEPS[k] steps (k = 0: a pair, 1: a longer run that
+    // spreads the launch gap between replays over more steps)
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graph_failed = false;
 };
 
@@ -523,6 +525,12 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     StepState st0;
     std::memset(&st0, 0, sizeof st0);
     for (int d = 0; d < 6; ++d) st0.box[0][d] = st0.box[1][d] = box[d];
+    // Sec. 3.1.2: e0 (n / r_c) |(r - r_c) / r_c|^(n - 1) for node distances 0 < r < r_c
+    for (int d2 = 1; d2 < 16; ++d2) {
+        const double r = std::sqrt((double)d2), rc = h->cfg.r_c;
+        st0.rep_mag[d2] = r < rc ? h->cfg.e0 * (h->cfg.n_exp / rc) * std::pow(std::fabs((r - rc) / rc), h->cfg.n_exp - 1.0)
+                                 : 0.0;
+    }
     int rc = h->q == 27 ? (h->prec == PF_LBM_FP64   ? init_device<double, D3Q27>(h, bodies, rho0, phi0, bd, st0)
                            : h->prec == PF_LBM_FP32 ? init_device<float, D3Q27>(h, bodies, rho0, phi0, bd, st0)
                                                     : init_device<half_t, D3Q27>(h, bodies, rho0, phi0, bd, st0))
@@ -550,10 +558,20 @@ int eager_step(pf_lbm *h) {
                                     : enqueue_step<half_t, D3Q19>(h);
 }
 
-// capture an even/odd step pair on the handle's stream into an executable graph; on any failure
-// the handle keeps launching kernels one by one
-bool ensure_graph(pf_lbm *h) {
-    if (h->graph) return true;
+constexpr int GRAPH_STEPS[2] = {2, 8};
+
+void drop_graphs(pf_lbm *h) {
+    for (hipGraphExec_t &g : h->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    h->graph_failed = false;
+}
+
+// capture GRAPH_STEPS[k] steps (an even number, starting at an even step) on the handle's
+// stream into an executable graph; on any failure the handle keeps launching kernels one by one
+bool ensure_graph(pf_lbm *h, int k) {
+    if (h->graph[k]) return true;
     if (h->graph_failed || !h->stream || (h->steps & 1)) return false;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
@@ -562,8 +580,8 @@ bool ensure_graph(pf_lbm *h) {
         return false;
     }
     const long long s0 = h->steps;
-    int rc = eager_step(h);
-    if (rc == PF_LBM_OK) rc = eager_step(h);
+    int rc = PF_LBM_OK;
+    for (int j = 0; j < GRAPH_STEPS[k] && rc == PF_LBM_OK; ++j) rc = eager_step(h);
     h->steps = s0;
     const hipError_t e = hipStreamEndCapture(h->stream, &g);
     if (rc != PF_LBM_OK || e != hipSuccess || !g) {
@@ -572,11 +590,11 @@ bool ensure_graph(pf_lbm *h) {
         h->graph_failed = true;
         return false;
     }
-    const hipError_t e2 = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    const hipError_t e2 = hipGraphInstantiate(&h->graph[k], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e2 != hipSuccess) {
         (void)hipGetLastError();
-        h->graph = nullptr;
+        h->graph[k] = nullptr;
         h->graph_failed = true;
         return false;
     }
@@ -594,10 +612,12 @@ int pf_lbm_step(pf_lbm *h, int32_t n_steps) {
         if (rc != PF_LBM_OK) return rc;
         --n;
     }
-    while (n >= 2 && !h->timing && ensure_graph(h)) {
-        HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
-        h->steps += 2;
-        n -= 2;
+    for (int k = 1; k >= 0; --k) {
+        while (n >= GRAPH_STEPS[k] && !h->timing && ensure_graph(h, k)) {
+            HIPCHK(h, hipGraphLaunch(h->graph[k], h->stream));
+            h->steps += GRAPH_STEPS[k];
+            n -= GRAPH_STEPS[k];
+        }
     }
     for (; n > 0; --n) {
         const int rc = eager_step(h);
@@ -769,10 +789,8 @@ int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3) {
     (void)hipEventDestroy(e1);
     h->rows = best_rows;
     h->psi_bs = best_bs;
-    // the captured step pair used the old shapes: capture again on the next pf_lbm_step
-    if (h->graph) (void)hipGraphExecDestroy(h->graph);
-    h->graph = nullptr;
-    h->graph_failed = false;
+    // the captured steps used the old shapes: capture again on the next pf_lbm_step
+    drop_graphs(h);
     if (out3) {
         out3[0] = best_rows;
         out3[1] = best_bs;
@@ -783,7 +801,7 @@ int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3) {
 
 void pf_lbm_destroy(pf_lbm *h) {
     if (!h) return;
-    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    drop_graphs(h);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
 }

@@ -150,8 +150,9 @@ def test_two_spheres_full_size_fp32(oracle_mod, torch_cuda):
 
 
 def test_graph_replay_matches_eager_launches(torch_cuda):
-    """The step pair captured in a HIP graph and replayed gives the same bits as launching the
-    kernels one by one (timing mode launches eagerly); replays alternate with host reads."""
+    """The step sequences captured in HIP graphs (pairs and runs of eight steps) and replayed give
+    the same bits as launching the kernels one by one (timing mode launches eagerly); replays
+    alternate with host reads and start at odd and even steps."""
     from paper_1902_10432_amd.simulation import Simulation
     w = tiny_moving_body(second_body=True)
     w.params["e0"] = 0.5
