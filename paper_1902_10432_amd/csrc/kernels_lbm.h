@@ -1,34 +1,11 @@
-// Fluid kernels of the step: pseudopotential, fused force + Guo-BGK collision + push streaming
-// with moving-wall bounce-back, and the per-body force/torque sums with the rigid-body update.
+// Fluid kernels of the step: fused force + Guo-BGK collision + push streaming with moving-wall
+// bounce-back, and the per-body force/torque sums (the pseudopotential pass, which also closes
+// the previous step's node conversions, is in kernels_pf.h).
 #pragma once
 
 #include "device_common.h"
 
 namespace pfl {
-
-// Pseudopotential psi = 1 - exp(-rho/rho0) of every fluid node; a solid node carries the value
-// of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.
-// psi_ref: the pseudopotential of the previous step (reference density of the FP16 form).
-template <typename S, class L>
-__global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, const S *__restrict__ f, const cell_t *__restrict__ mask,
-                                             const BodyDev *__restrict__ bodies, const ArT<S> *__restrict__ psi_ref,
-                                             ArT<S> *__restrict__ psi) {
-    using T = ArT<S>;
-    const int idx = xcd_block(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
-    if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed
-    const cell_t m = mask[idx];
-    T out;
-    if (m & C_SOLID) {
-        out = (T)bodies[owner_of(m)].psi_s;
-    } else {
-        // the weights sum to one: rho = R + sum of the stored deviations in the FP16 form
-        T r = T(0);
-        if constexpr (sizeof(S) == 2) r = ref_density(psi_ref[idx], p.rho0);
-        sfor<L::Q>([&](auto I) { r += (T)f[(long long)I * p.Np + idx]; });
-        out = -expm1(-r * p.inv_rho0);
-    }
-    psi[idx] = out;
-}
 
 // periodic neighbour offsets of one cell as unsigned index deltas (the sum with the cell index
 // wraps modulo 2^32 onto the neighbour's index, which lets loads use a scalar base + 32-bit

@@ -577,6 +577,7 @@ __device__ __forceinline__ T feq_dir(T rho, T ux, T uy, T uz) {
 // neighbours
 __device__ __forceinline__ int fluid_count(const cell_t *mask, int x, int y, int z, int nx, int ny, int nz, double r2) {
     int cnt = 0;
+#pragma unroll 1
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
@@ -593,6 +594,7 @@ __device__ __forceinline__ int fluid_count(const cell_t *mask, int x, int y, int
 __device__ __forceinline__ int conversion_radius(const cell_t *mask, int x, int y, int z, int nx, int ny, int nz,
                                                  double RA, double &r2sel) {
     const double radii2[3] = {RA * RA, 2.0, 3.0};
+#pragma unroll 1
     for (int t = 0; t < 3; ++t) {
         if (t > 0 && radii2[t] <= RA * RA + 1e-9) continue;
         const int c = fluid_count(mask, x, y, z, nx, ny, nz, radii2[t]);
@@ -743,48 +745,47 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
                                              int z, uint32_t idx, int empty, unsigned long long &lost) {
     using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
+    // runtime loops: this runs inside the pseudopotential pass, whose register budget it must
+    // not raise (events are rare)
     const cell_t m = mask[idx];
     if (empty == 2 || (empty == 1 && (m & C_F2S))) {
         double r2;
         if (conversion_radius(mask, x, y, z, nx, ny, nz, p.R_A, r2) == 0) ++lost;
         const T rr = sizeof(S) == 2 ? ref_density(psi[idx], p.rho0) : T(0);
-        sfor<L::Q>([&](auto I) {
-            f[(long long)I * p.Np + idx] = pop_put<S>(T(0), Dir<decltype(I)::value, L>::template w<T>() * rr);
-        });
+#pragma unroll 1
+        for (int i = 0; i < L::Q; ++i) {
+            const int c2 = kCX[i] * kCX[i] + kCY[i] * kCY[i] + kCZ[i] * kCZ[i];
+            f[(long long)i * p.Np + idx] = pop_put<S>(T(0), T(L::wshell[c2]) * rr);
+        }
     }
     uint32_t bits = 0;
     if constexpr (L::kBits) {
-        const NbrU ne1(x, y, z, nx, ny, nz, 1);
-        sfor<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (i > 0)
-                if (mask[ne1.template at<i>(idx)] & C_SOLID) bits |= 1u << i;
-        });
+        const Nbr nb(x, y, z, nx, ny, nz);
+#pragma unroll 1
+        for (int i = 1; i < L::Q; ++i)
+            if (mask[(int)idx + nb.off_rt(i)] & C_SOLID) bits |= 1u << i;
     }
     const cell_t mn = (m & ~(C_F2S | C_S2F | C_NBMASK)) | bits;
     if (mn != m) mask[idx] = mn;
 }
 
-// Closing pass of the step.  With full != 0 (initialisation) or an overflowed event list, every
-// box node is refreshed; otherwise only the nodes whose words can have changed: each event node
-// (emptied if it became solid) and the 18 nodes that have it as a neighbour.  Without events
-// the kernel returns at once.
+// Closing work of a step's node conversions, run after the conversion gather: with full != 0
+// (initialisation) or an overflowed event list, every node of the box is refreshed; otherwise
+// only the nodes whose words can have changed: each event node (emptied if it became solid) and
+// the 18 nodes that have it as a neighbour.  Threads gtid (of gstride) take the work in turn.
 template <typename S, class L>
-__global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepState *st, cell_t *__restrict__ mask, S *f,
-                                              const ArT<S> *__restrict__ psi, const uint32_t *__restrict__ evlist,
-                                              uint32_t evcap, int full) {
-    const uint32_t nev = st->n_events;
-    if (!full && !nev) return;
+__device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t *box, uint32_t nev, StepState *st,
+                                            cell_t *mask, S *f, const ArT<S> *psi, const uint32_t *evlist,
+                                            uint32_t evcap, int full, int gtid, int gstride) {
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int gtid = blockIdx.x * 256 + threadIdx.x, gstride = gridDim.x * 256;
     unsigned long long lost = 0;
     if (full || nev > evcap) {
-        const BoxIter it(st->box[parity], nx, ny, nz);
+        const BoxIter it(box, nx, ny, nz);
         for (int k = gtid; k < it.vol; k += gstride) {
             int u[3], c[3];
             it.cell(k, u, c);
             refresh_node<S, L>(p, mask, f, psi, c[0], c[1], c[2], (uint32_t)(c[0] + nx * (c[1] + ny * c[2])), full ? 0 : 1,
-                         lost);
+                               lost);
         }
     } else {
         // D3Q19: the event node and the 18 nodes whose bit for it may change; D3Q27 keeps no
@@ -798,10 +799,53 @@ __global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepSta
             // node whose neighbour in direction i is e
             const int x = wrapi(ex - kCX[i], nx), y = wrapi(ey - kCY[i], ny), z = wrapi(ez - kCZ[i], nz);
             refresh_node<S, L>(p, mask, f, psi, x, y, z, (uint32_t)(x + nx * (y + ny * z)),
-                         (i == 0 && (ent & 0x80000000u)) ? 2 : 0, lost);
+                               (i == 0 && (ent & 0x80000000u)) ? 2 : 0, lost);
         }
     }
     if (lost) atomicAdd(&st->n_lost, lost);  // rare
+}
+
+// Every box node refreshed (initialisation: neighbour bits of the first cell words).
+template <typename S, class L>
+__global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepState *st, cell_t *__restrict__ mask, S *f,
+                                              const ArT<S> *__restrict__ psi) {
+    post_events<S, L>(p, st->box[parity], 0u, st, mask, f, psi, nullptr, 0u, 1, blockIdx.x * 256 + threadIdx.x,
+                      gridDim.x * 256);
+}
+
+// Pseudopotential psi = 1 - exp(-rho/rho0) of every fluid node; a solid node carries the value
+// of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.
+// psi_ref: the pseudopotential of the previous step (reference density of the FP16 form).
+//
+// The pass first closes the previous step's node conversions (post_events on its event list,
+// box and pseudopotential): it touches only nodes that became solid (populations this pass does
+// not read) and the neighbour bits of cell words (which it does not read either), and the
+// collision pass after it sees the result.  Without events every thread returns from it at once;
+// keeping it here saves a launch per step.
+template <typename S, class L>
+__global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, int parity, StepState *st, S *f, cell_t *mask,
+                                             const BodyDev *__restrict__ bodies, const ArT<S> *__restrict__ psi_ref,
+                                             ArT<S> *__restrict__ psi, const uint32_t *__restrict__ evlist,
+                                             uint32_t evcap) {
+    using T = ArT<S>;
+    const uint32_t nev = st ? st->n_events : 0u;
+    if (nev)
+        post_events<S, L>(p, st->box[parity ^ 1], nev, st, mask, f, psi_ref, evlist, evcap, 0,
+                          blockIdx.x * (int)blockDim.x + threadIdx.x, gridDim.x * (int)blockDim.x);
+    const int idx = xcd_block(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
+    if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed
+    const cell_t m = mask[idx];
+    T out;
+    if (m & C_SOLID) {
+        out = (T)bodies[owner_of(m)].psi_s;
+    } else {
+        // the weights sum to one: rho = R + sum of the stored deviations in the FP16 form
+        T r = T(0);
+        if constexpr (sizeof(S) == 2) r = ref_density(psi_ref[idx], p.rho0);
+        sfor<L::Q>([&](auto I) { r += (T)f[(long long)I * p.Np + idx]; });
+        out = -expm1(-r * p.inv_rho0);
+    }
+    psi[idx] = out;
 }
 
 // ---- initialisation and read-out helpers ------------------------------------------------------

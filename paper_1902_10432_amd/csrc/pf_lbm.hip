@@ -303,7 +303,9 @@ int enqueue_step(pf_lbm *h) {
         ++h->timed;
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
-    k_psi<S, Lat><<<gd, dim3(h->psi_bs), 0, s>>>(p, fc, mask, cur, psi_prev, psi);
+    uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
+    k_psi<S, Lat><<<gd, dim3(h->psi_bs), 0, s>>>(p, par, h->nb > 0 ? st : nullptr, fc, mask, cur, psi_prev, psi, evlist,
+                                                 EV_CAP);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
     k_collide_stream<S, Lat><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + h->rows - 1) / h->rows, h->cfg.nz),
                                dim3(64, h->rows), 0, s>>>(
@@ -319,12 +321,11 @@ int enqueue_step(pf_lbm *h) {
                                         (double *)(h->ws + h->L.hist), HIST_CAP);
         k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA, nullptr, 0);
         k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB, nullptr, 0);
-        uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
         launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
-        // conversion passes: usually return at once (no node changed side), so a small grid
+        // conversion gather: usually returns at once (no node changed side), so a small grid; the
+        // next step's pseudopotential pass closes the conversions
         const dim3 ge(std::min(h->box_grid, 64));
         k_convert_gather<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP);
-        k_post<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP, 0);
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[3], s));
     HIPCHK(h, hipGetLastError());
@@ -376,8 +377,7 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
     HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)Lat::Q * h->Np * sizeof(S), s));
     // neighbour bits of the cell words
     if (h->nb > 0)
-        k_post<S, Lat><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA, psi_init,
-                                                        (const uint32_t *)(h->ws + h->L.evlist), EV_CAP, 1);
+        k_post<S, Lat><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA, psi_init);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
     return PF_LBM_OK;
