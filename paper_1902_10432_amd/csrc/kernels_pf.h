@@ -63,6 +63,9 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
     __shared__ double lb[PF_LBM_MAX_BODIES][9];  // X, V, W of each body for this sweep
     const int tid = threadIdx.x;
     const int nbod = p.nb;
+    // the box words are read first so that their latency overlaps the body-table reads
+    int32_t box[6];
+    for (int d = 0; d < 6; ++d) box[d] = st->box[parity][d];
     if (AX == 0) {
         block_totals(fpart, fblk, nbod * 6, tot);
         if (tid < nbod) {
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
             }
     }
     __syncthreads();
-    const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
+    const BoxIter it(box, p.nx, p.ny, p.nz);
     const int n[3] = {p.nx, p.ny, p.nz};
     const long long Np = p.Np;
     const int step = AX == 0 ? 1 : (AX == 1 ? p.nx : p.nx * p.ny);
@@ -406,12 +409,16 @@ __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, Ste
     __shared__ double hh[NP];
     const int tid = threadIdx.x;
     const int nbod = p.nb, np1 = nbod + 1;
-    for (int k = tid; k < NP * NP; k += 256) sg[k] = 0.0;
-    __syncthreads();
-    for (int k = tid; k < np1 * np1; k += 256) sg[(k / np1) * NP + (k % np1)] = sigma[k];
+    // the box words are read first so that their latency overlaps the table reads
+    int32_t box[6];
+    for (int d = 0; d < 6; ++d) box[d] = st->box[parity][d];
+    for (int k = tid; k < NP * NP; k += 256) {
+        const int r = k / NP, c = k % NP;
+        sg[k] = (r < np1 && c < np1) ? sigma[r * np1 + c] : 0.0;
+    }
     if (tid < NP) hh[tid] = (tid == 0 || tid > nbod) ? 0.0 : bodies[tid - 1].h;
     __syncthreads();
-    const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
+    const BoxIter it(box, p.nx, p.ny, p.nz);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
     const bool kin = (p.flags & PF_LBM_KINETICS) != 0;

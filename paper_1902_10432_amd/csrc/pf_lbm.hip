@@ -558,7 +558,7 @@ int eager_step(pf_lbm *h) {
                                     : enqueue_step<half_t, D3Q19>(h);
 }
 
-constexpr int GRAPH_STEPS[2] = {2, 8};
+constexpr int GRAPH_STEPS[2] = {2, 32};
 
 void drop_graphs(pf_lbm *h) {
     for (hipGraphExec_t &g : h->graph) {

@@ -150,7 +150,7 @@ def test_two_spheres_full_size_fp32(oracle_mod, torch_cuda):
 
 
 def test_graph_replay_matches_eager_launches(torch_cuda):
-    """The step sequences captured in HIP graphs (pairs and runs of eight steps) and replayed give
+    """The step sequences captured in HIP graphs (pairs and runs of 32 steps) and replayed give
     the same bits as launching the kernels one by one (timing mode launches eagerly); replays
     alternate with host reads and start at odd and even steps."""
     from paper_1902_10432_amd.simulation import Simulation
@@ -159,7 +159,7 @@ def test_graph_replay_matches_eager_launches(torch_cuda):
     g = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision="fp64")
     e = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision="fp64")
     e.timing(True)
-    for chunk in (7, 10, 12, 1, 20):
+    for chunk in (7, 10, 12, 1, 20, 37):
         g.step(chunk)
         e.step(chunk)
         assert np.array_equal(g.rho(), e.rho())
