@@ -51,18 +51,24 @@ MASK_BYTES = 4  # one 32-bit cell word per node
 FORMS = {"fp64": (8, 8), "fp32": (4, 4), "fp16": (2, 4)}
 
 
+def _bit_bytes(q: int) -> int:
+    """D3Q27 keeps the solid-neighbour bits in a word of their own (D3Q19: in the cell word)."""
+    return 4 if q == 27 else 0
+
+
 def step_bytes_per_cell(pop: int, arith: int, q: int = 19) -> float:
     """Algorithmic bytes of one coupled step per node: q populations read and written, the
-    pseudopotential written once and read once, the cell word read once (the phase-field work on
-    the box around the bodies is not counted)."""
-    return 2 * q * pop + 2 * arith + MASK_BYTES
+    pseudopotential written once and read once, the cell word (and on D3Q27 the neighbour-bit
+    word) read once (the phase-field work on the box around the bodies is not counted)."""
+    return 2 * q * pop + 2 * arith + MASK_BYTES + _bit_bytes(q)
 
 
 def kernel_bytes(n_fluid: int, n_solid: int, pop: int, arith: int, q: int = 19) -> float:
     """Algorithmic bytes of one collide-stream launch: a fluid node reads and writes its q
-    populations and reads its own pseudopotential and cell word (neighbour values are re-reads
-    of the same arrays); a solid node reads its cell word only."""
-    return n_fluid * (2 * q * pop + arith + MASK_BYTES) + n_solid * float(MASK_BYTES)
+    populations and reads its own pseudopotential and cell word (and on D3Q27 its neighbour-bit
+    word; neighbour values are re-reads of the same arrays); a solid node reads its cell word
+    only."""
+    return n_fluid * (2 * q * pop + arith + MASK_BYTES + _bit_bytes(q)) + n_solid * float(MASK_BYTES)
 
 
 def copy_calibration(mib: int, reps: int) -> int:

@@ -28,7 +28,7 @@ struct D3Q19 {
 };
 struct D3Q27 {
     static constexpr int Q = 27;
-    // 26 neighbour bits do not fit beside the flags: kernels read the neighbours' words instead
+    // 26 neighbour bits do not fit beside the flags: they live in a word array of their own
     static constexpr bool kBits = false;
     static constexpr double wshell[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
 };

@@ -108,7 +108,8 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
                                                         const ArT<S> *__restrict__ psi_prev,
                                                         const cell_t *__restrict__ mask,
                                                         BodyDev *bodies, int parity, StepState *st,
-                                                        const ClassifyPart *__restrict__ cpart, int cblk) {
+                                                        const ClassifyPart *__restrict__ cpart, int cblk,
+                                                        const uint32_t *__restrict__ nbw) {
     using T = ArT<S>;
     if (cpart && (blockIdx.x | blockIdx.y | blockIdx.z) == 0)
         publish_step_state((int)threadIdx.y, (int)blockDim.y, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart,
@@ -119,19 +120,13 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
     const cell_t w0 = mask[idx];
     if (w0 & C_SOLID) return;
-    // bit i: the neighbour in direction i is solid (D3Q19: kept in the word; D3Q27: read here)
-    uint32_t solid_dirs = 0;
-    if constexpr (L::kBits) {
+    // bit i: the neighbour in direction i is solid (D3Q19: kept in the cell word; D3Q27: the
+    // neighbour-bit word of the node)
+    uint32_t solid_dirs;
+    if constexpr (L::kBits)
         solid_dirs = w0 & C_NBMASK;
-    } else {
-        const NbrU nm(x, y, z, nx, ny, nz, (int)sizeof(cell_t));
-        const uint32_t im = idx * (uint32_t)sizeof(cell_t);
-        sfor<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (i > 0)
-                if (ldb(mask, nm.template at<i>(im)) & C_SOLID) solid_dirs |= 1u << i;
-        });
-    }
+    else
+        solid_dirs = nbw[idx];
     const uint32_t ib = idx * (uint32_t)sizeof(T);      // psi (arithmetic type)
     const uint32_t is = idx * (uint32_t)sizeof(S);      // populations (storage type)
     const NbrU nb(x, y, z, nx, ny, nz, (int)sizeof(T));
@@ -281,7 +276,8 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                                                      const S *__restrict__ fpost, const ArT<S> *__restrict__ psi,
                                                      const ArT<S> *__restrict__ psi_prev,
                                                      const cell_t *__restrict__ mask,
-                                                     const BodyDev *__restrict__ bodies, double *part) {
+                                                     const BodyDev *__restrict__ bodies, double *part,
+                                                     const uint32_t *__restrict__ nbw) {
     using T = ArT<S>;
     constexpr int W = force_waves<T, L>(), NT = 64 * W;
     __shared__ double acc[W][PF_LBM_MAX_BODIES][6];
@@ -318,17 +314,10 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                 fluid = true;
                 uint32_t mo[L::Q];  // words of the neighbours
                 const NbrU ne(x, y, z, nx, ny, nz, 1);
-                if constexpr (L::kBits) {
+                if constexpr (L::kBits)
                     nbits = w0 & C_NBMASK;
-                } else {
-                    sfor<L::Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        if constexpr (i > 0) {
-                            mo[i] = ldb(mask, ne.template at<i>((uint32_t)idx) * 4u);
-                            if (mo[i] & C_SOLID) nbits |= 1u << i;
-                        }
-                    });
-                }
+                else
+                    nbits = nbw[idx];
                 if (nbits) {
                     // Every gather of the node is issued in one round and unconditionally (the
                     // neighbour values are cache-served), so the per-link selects below wait for
@@ -342,7 +331,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                         constexpr int i = decltype(I)::value;
                         if constexpr (i > 0) {
                             const uint32_t n = ne.template at<i>((uint32_t)idx);
-                            if constexpr (L::kBits) mo[i] = ldb(mask, n * 4u);
+                            mo[i] = ldb(mask, n * 4u);
                             fo[i] = ldb(fpost + (long long)Dir<i, L>::opp * Np, is);
                             pn[i] = ldb(psi, n * (uint32_t)sizeof(T));
                         }

@@ -748,8 +748,8 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
 // empty: 0 never, 1 when the word carries the "became solid" mark (one visit per node), 2 always
 // (the caller knows the node became solid).
 template <typename S, class L>
-__device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask, S *f, const ArT<S> *psi, int x, int y,
-                                             int z, uint32_t idx, int empty, unsigned long long &lost) {
+__device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask, uint32_t *nbw, S *f, const ArT<S> *psi,
+                                             int x, int y, int z, uint32_t idx, int empty, unsigned long long &lost) {
     using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     // runtime loops: this runs inside the pseudopotential pass, whose register budget it must
@@ -766,14 +766,17 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
         }
     }
     uint32_t bits = 0;
-    if constexpr (L::kBits) {
+    {
         const Nbr nb(x, y, z, nx, ny, nz);
 #pragma unroll 1
         for (int i = 1; i < L::Q; ++i)
             if (mask[(int)idx + nb.off_rt(i)] & C_SOLID) bits |= 1u << i;
     }
-    const cell_t mn = (m & ~(C_F2S | C_S2F | C_NBMASK)) | bits;
+    // D3Q19: the bits in the cell word; D3Q27: in the neighbour-bit word
+    const cell_t mn = (m & ~(C_F2S | C_S2F | C_NBMASK)) | (L::kBits ? bits : 0u);
     if (mn != m) mask[idx] = mn;
+    if constexpr (!L::kBits)
+        if (nbw[idx] != bits) nbw[idx] = bits;
 }
 
 // Closing work of a step's node conversions, run after the conversion gather: with full != 0
@@ -782,8 +785,9 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
 // the 18 nodes that have it as a neighbour.  Threads gtid (of gstride) take the work in turn.
 template <typename S, class L>
 __device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t *box, uint32_t nev, StepState *st,
-                                            cell_t *mask, S *f, const ArT<S> *psi, const uint32_t *evlist,
-                                            uint32_t evcap, int full, int gtid, int gstride) {
+                                            cell_t *mask, uint32_t *nbw, S *f, const ArT<S> *psi,
+                                            const uint32_t *evlist, uint32_t evcap, int full, int gtid,
+                                            int gstride) {
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     unsigned long long lost = 0;
     if (full || nev > evcap) {
@@ -791,13 +795,12 @@ __device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t 
         for (int k = gtid; k < it.vol; k += gstride) {
             int u[3], c[3];
             it.cell(k, u, c);
-            refresh_node<S, L>(p, mask, f, psi, c[0], c[1], c[2], (uint32_t)(c[0] + nx * (c[1] + ny * c[2])), full ? 0 : 1,
-                               lost);
+            refresh_node<S, L>(p, mask, nbw, f, psi, c[0], c[1], c[2], (uint32_t)(c[0] + nx * (c[1] + ny * c[2])),
+                               full ? 0 : 1, lost);
         }
     } else {
-        // D3Q19: the event node and the 18 nodes whose bit for it may change; D3Q27 keeps no
-        // bits, so only the event node itself
-        constexpr int NR = L::kBits ? L::Q : 1;
+        // the event node and the Q - 1 nodes whose bit for it may change
+        constexpr int NR = L::Q;
         for (int j = gtid; j < (int)nev * NR; j += gstride) {
             const uint32_t ent = evlist[j / NR];
             const int i = j % NR;
@@ -805,7 +808,7 @@ __device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t 
             const int ex = (int)(e % (uint32_t)nx), ey = (int)((e / (uint32_t)nx) % (uint32_t)ny), ez = (int)(e / ((uint32_t)nx * ny));
             // node whose neighbour in direction i is e
             const int x = wrapi(ex - kCX[i], nx), y = wrapi(ey - kCY[i], ny), z = wrapi(ez - kCZ[i], nz);
-            refresh_node<S, L>(p, mask, f, psi, x, y, z, (uint32_t)(x + nx * (y + ny * z)),
+            refresh_node<S, L>(p, mask, nbw, f, psi, x, y, z, (uint32_t)(x + nx * (y + ny * z)),
                                (i == 0 && (ent & 0x80000000u)) ? 2 : 0, lost);
         }
     }
@@ -814,9 +817,9 @@ __device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t 
 
 // Every box node refreshed (initialisation: neighbour bits of the first cell words).
 template <typename S, class L>
-__global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepState *st, cell_t *__restrict__ mask, S *f,
-                                              const ArT<S> *__restrict__ psi) {
-    post_events<S, L>(p, st->box[parity], 0u, st, mask, f, psi, nullptr, 0u, 1, blockIdx.x * 256 + threadIdx.x,
+__global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepState *st, cell_t *__restrict__ mask,
+                                              uint32_t *nbw, S *f, const ArT<S> *__restrict__ psi) {
+    post_events<S, L>(p, st->box[parity], 0u, st, mask, nbw, f, psi, nullptr, 0u, 1, blockIdx.x * 256 + threadIdx.x,
                       gridDim.x * 256);
 }
 
@@ -831,13 +834,13 @@ __global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepSta
 // keeping it here saves a launch per step.
 template <typename S, class L>
 __global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, int parity, StepState *st, S *f, cell_t *mask,
-                                             const BodyDev *__restrict__ bodies, const ArT<S> *__restrict__ psi_ref,
-                                             ArT<S> *__restrict__ psi, const uint32_t *__restrict__ evlist,
-                                             uint32_t evcap) {
+                                             uint32_t *nbw, const BodyDev *__restrict__ bodies,
+                                             const ArT<S> *__restrict__ psi_ref, ArT<S> *__restrict__ psi,
+                                             const uint32_t *__restrict__ evlist, uint32_t evcap) {
     using T = ArT<S>;
     const uint32_t nev = st ? st->n_events : 0u;
     if (nev)
-        post_events<S, L>(p, st->box[parity ^ 1], nev, st, mask, f, psi_ref, evlist, evcap, 0,
+        post_events<S, L>(p, st->box[parity ^ 1], nev, st, mask, nbw, f, psi_ref, evlist, evcap, 0,
                           blockIdx.x * (int)blockDim.x + threadIdx.x, gridDim.x * (int)blockDim.x);
     const int idx = xcd_block(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
     if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed

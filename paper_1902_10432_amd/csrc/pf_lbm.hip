@@ -30,7 +30,7 @@ constexpr int HIST_CAP = 8192;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t fA, fB, psi, psiB, phiA, phiB, mask, bodies, state, sigma, pforce, cpart, evlist, hist, total;
+    size_t fA, fB, psi, psiB, phiA, phiB, mask, nbw, bodies, state, sigma, pforce, cpart, evlist, hist, total;
 };
 
 }  // namespace
@@ -108,6 +108,8 @@ Layout make_layout(long long Np, int nb, int prec, int q, int cpart_n, int force
     L.phiA = take((size_t)std::max(nb, 1) * Np * sizeof(double));
     L.phiB = take((size_t)std::max(nb, 1) * Np * sizeof(double));
     L.mask = take((size_t)Np * sizeof(cell_t));
+    // D3Q27: one word of solid-neighbour bits per node (D3Q19 keeps them in the cell word)
+    L.nbw = q == 27 ? take((size_t)Np * sizeof(uint32_t)) : 0;
     L.bodies = take(2 * sizeof(BodyDev) * std::max(nb, 1));  // current / next, by step parity
     L.state = take(sizeof(StepState));
     L.sigma = take(sizeof(double) * (nb + 1) * (nb + 1));
@@ -281,6 +283,7 @@ int enqueue_step(pf_lbm *h) {
     T *psi_prev = (T *)(h->ws + (par ? h->L.psi : h->L.psiB));    // the previous step
     double *phiA = (double *)(h->ws + h->L.phiA), *phiB = (double *)(h->ws + h->L.phiB);
     cell_t *mask = (cell_t *)(h->ws + h->L.mask);
+    uint32_t *nbw = Lat::Q == 27 ? (uint32_t *)(h->ws + h->L.nbw) : nullptr;
     BodyDev *btab = (BodyDev *)(h->ws + h->L.bodies);
     const int nbm = std::max(h->nb, 1);
     BodyDev *cur = btab + par * nbm, *next = btab + (par ^ 1) * nbm;
@@ -304,18 +307,18 @@ int enqueue_step(pf_lbm *h) {
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
     uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
-    k_psi<S, Lat><<<gd, dim3(h->psi_bs), 0, s>>>(p, par, h->nb > 0 ? st : nullptr, fc, mask, cur, psi_prev, psi, evlist,
-                                                 EV_CAP);
+    k_psi<S, Lat><<<gd, dim3(h->psi_bs), 0, s>>>(p, par, h->nb > 0 ? st : nullptr, fc, mask, nbw, cur, psi_prev, psi,
+                                                 evlist, EV_CAP);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
     k_collide_stream<S, Lat><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + h->rows - 1) / h->rows, h->cfg.nz),
                                dim3(64, h->rows), 0, s>>>(
-        p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->cgrid);
+        p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->cgrid, nbw);
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
         const dim3 gb(h->box_grid);
         k_body_forces<S, Lat><<<dim3(fbk), dim3(64 * force_waves<T, Lat>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev,
-                                                                                      mask, cur, pforce);
+                                                                                      mask, cur, pforce, nbw);
         // one kernel per sweep; the phase fields end in buffer A every step
         k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB,
                                         (double *)(h->ws + h->L.hist), HIST_CAP);
@@ -353,6 +356,8 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
     HIPCHK(h, hipMemcpyAsync(h->ws + h->L.sigma, h->sigma.data(), sizeof(double) * h->sigma.size(),
                              hipMemcpyHostToDevice, s));
     k_zero_mask<T><<<gd, b, 0, s>>>(p, mask);
+    uint32_t *nbw = Lat::Q == 27 ? (uint32_t *)(h->ws + h->L.nbw) : nullptr;
+    if (nbw) k_zero_mask<T><<<gd, b, 0, s>>>(p, nbw);
     // phase fields, one body at a time through the staging area
     for (int a = 0; a < h->nb; ++a) {
         HIPCHK(h, hipMemcpyAsync(tmp, phi0 + (size_t)a * h->N, sizeof(double) * h->N, hipMemcpyHostToDevice, s));
@@ -377,7 +382,7 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
     HIPCHK(h, hipMemsetAsync(fB, 0, (size_t)Lat::Q * h->Np * sizeof(S), s));
     // neighbour bits of the cell words
     if (h->nb > 0)
-        k_post<S, Lat><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, fA, psi_init);
+        k_post<S, Lat><<<dim3(h->box_grid), b, 0, s>>>(p, 0, st, mask, nbw, fA, psi_init);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
     return PF_LBM_OK;
