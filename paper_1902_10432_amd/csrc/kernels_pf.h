@@ -54,7 +54,7 @@ __device__ __forceinline__ void block_totals(const double *part, int nblk, int K
 // X += V, omega += I^-1 T; block 0 publishes the result (with F, T) in the next table, which the
 // later kernels of the step read.
 // hist (first sweep): ring of hcap steps of per-body force and torque, [step][body][6]
-template <typename T, int AX>
+template <typename T, int AX, int NBMAX>
 __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState *st, const BodyDev *__restrict__ cur,
                                                 BodyDev *__restrict__ next, const double *__restrict__ fpart, int fblk,
                                                 const double *__restrict__ src, double *__restrict__ dst,
@@ -142,18 +142,35 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
             off[s + 2] = idx + (wrap2(i + s, L) - i) * step;
             in[s + 2] = it.inside(AX, u[AX] + s);
         }
-        for (int a = 0; a < nbod; ++a) {
-            // velocity component along AX at this sweep line
-            const double r1 = mimg_r((double)c[A1] - lb[a][A1], n[A1], p.inv_n[A1]);
-            const double r2 = mimg_r((double)c[A2] - lb[a][A2], n[A2], p.inv_n[A2]);
-            const double uu = lb[a][3 + AX] + (lb[a][6 + A1] * r2 - lb[a][6 + A2] * r1);
-            const double *s0 = src + (long long)a * Np;
-            const double vm2 = in[0] ? s0[off[0]] : 0.0, vm1 = in[1] ? s0[off[1]] : 0.0, v0 = s0[off[2]],
-                         v1 = in[3] ? s0[off[3]] : 0.0, v2 = in[4] ? s0[off[4]] : 0.0;
-            const double Fp = mc_flux(uu, vm1, v0, v1, v2);
-            const double Fm = mc_flux(uu, vm2, vm1, v0, v1);
-            dst[(long long)a * Np + idx] = v0 - (Fp - Fm);
-            if (fabs(uu) > 1.0 && (vm2 != 0.0 || vm1 != 0.0 || v0 != 0.0 || v1 != 0.0 || v2 != 0.0)) cfl = 1;
+        // the stencils of up to four phases first, loaded unconditionally (the wrapped indices
+        // lie in the grid; values outside the box are masked), so that one memory latency covers
+        // the group
+        constexpr int G = NBMAX < 4 ? NBMAX : 4;
+        for (int a0 = 0; a0 < nbod; a0 += G) {
+            double sv[G][5];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const double *s0 = src + (long long)(a0 + g < nbod ? a0 + g : a0) * Np;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const double t = s0[off[q]];
+                    sv[g][q] = in[q] ? t : 0.0;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int a = a0 + g;
+                if (a >= nbod) break;
+                // velocity component along AX at this sweep line
+                const double r1 = mimg_r((double)c[A1] - lb[a][A1], n[A1], p.inv_n[A1]);
+                const double r2 = mimg_r((double)c[A2] - lb[a][A2], n[A2], p.inv_n[A2]);
+                const double uu = lb[a][3 + AX] + (lb[a][6 + A1] * r2 - lb[a][6 + A2] * r1);
+                const double vm2 = sv[g][0], vm1 = sv[g][1], v0 = sv[g][2], v1 = sv[g][3], v2 = sv[g][4];
+                const double Fp = mc_flux(uu, vm1, v0, v1, v2);
+                const double Fm = mc_flux(uu, vm2, vm1, v0, v1);
+                dst[(long long)a * Np + idx] = v0 - (Fp - Fm);
+                if (fabs(uu) > 1.0 && (vm2 != 0.0 || vm1 != 0.0 || v0 != 0.0 || v1 != 0.0 || v2 != 0.0)) cfl = 1;
+            }
         }
     }
     if (cfl) atomicOr(&st->err, 2u);  // rare: only when the input breaks the CFL bound

@@ -272,6 +272,33 @@ void launch_phase_update(pf_lbm *h, const Prm<T> &p, int par, StepState *st, con
         k_phase_update<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
 }
 
+// the three advection sweeps x (with the rigid-body update), y, z: a -> b -> a -> b
+template <typename T, int NBMAX>
+void launch_advect_n(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *cur, BodyDev *next,
+                     const double *pforce, int fbk, double *a, double *b) {
+    const dim3 g(h->box_grid), bl(256);
+    hipStream_t s = h->stream;
+    k_advect<T, 0, NBMAX><<<g, bl, 0, s>>>(p, par, st, cur, next, pforce, fbk, a, b, (double *)(h->ws + h->L.hist),
+                                           HIST_CAP);
+    k_advect<T, 1, NBMAX><<<g, bl, 0, s>>>(p, par, st, cur, next, nullptr, 0, b, a, nullptr, 0);
+    k_advect<T, 2, NBMAX><<<g, bl, 0, s>>>(p, par, st, cur, next, nullptr, 0, a, b, nullptr, 0);
+}
+
+template <typename T>
+void launch_advect(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *cur, BodyDev *next,
+                   const double *pforce, int fbk, double *a, double *b) {
+    if (h->nb <= 1)
+        launch_advect_n<T, 1>(h, p, par, st, cur, next, pforce, fbk, a, b);
+    else if (h->nb <= 2)
+        launch_advect_n<T, 2>(h, p, par, st, cur, next, pforce, fbk, a, b);
+    else if (h->nb <= 4)
+        launch_advect_n<T, 4>(h, p, par, st, cur, next, pforce, fbk, a, b);
+    else if (h->nb <= 8)
+        launch_advect_n<T, 8>(h, p, par, st, cur, next, pforce, fbk, a, b);
+    else
+        launch_advect_n<T, 16>(h, p, par, st, cur, next, pforce, fbk, a, b);
+}
+
 // one time step (Sec. 3): fluid, body forces + rigid update, phase fields, reclassification
 template <typename S, class Lat>
 int enqueue_step(pf_lbm *h) {
@@ -316,14 +343,10 @@ int enqueue_step(pf_lbm *h) {
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
-        const dim3 gb(h->box_grid);
         k_body_forces<S, Lat><<<dim3(fbk), dim3(64 * force_waves<T, Lat>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev,
                                                                                       mask, cur, pforce, nbw);
         // one kernel per sweep; the phase fields end in buffer A every step
-        k_advect<T, 0><<<gb, b, 0, s>>>(p, par, st, cur, next, pforce, fbk, phiA, phiB,
-                                        (double *)(h->ws + h->L.hist), HIST_CAP);
-        k_advect<T, 1><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiB, phiA, nullptr, 0);
-        k_advect<T, 2><<<gb, b, 0, s>>>(p, par, st, cur, next, nullptr, 0, phiA, phiB, nullptr, 0);
+        launch_advect<T>(h, p, par, st, cur, next, pforce, fbk, phiA, phiB);
         launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
         // conversion gather: usually returns at once (no node changed side), so a small grid; the
         // next step's pseudopotential pass closes the conversions
@@ -475,10 +498,12 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     // box kernels: about one thread per cell of the initial box with room to grow (grid-stride
     // loops cover larger boxes), at most 4096 blocks
     const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
-    // box kernels: grid-stride over the box with at most two blocks per CU of the 256 (measured:
-    // 512 blocks beat 1024, 2048 and 256 on the 128^3 workload, the launch and drain of more
-    // blocks costing more than their extra parallelism gains)
-    const int box_grid = std::min(box_blocks, 512), force_grid = std::min((box_blocks + 3) / 4, 256);
+    // box kernels: grid-stride over the box with two blocks per CU of the 256, four for boxes
+    // above 2^20 cells (measured: on the 128^3 workload, 0.3 M cells, 512 blocks beat 256 and
+    // 1024, the launch and drain of more blocks costing more than their extra parallelism gains;
+    // on the 256^3 four-sphere workload 1024 beat 512 by 2 %)
+    const int box_grid = std::min(box_blocks, vol0 > (1LL << 20) ? 1024 : 512);
+    const int force_grid = std::min((box_blocks + 3) / 4, 256);
     const int cgrid = box_grid;
     const Layout L = make_layout(Np, n_bodies, cfg->precision, cfg->lattice, std::max(cgrid, box_grid), force_grid);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
