@@ -281,10 +281,18 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
     using T = ArT<S>;
     constexpr int W = force_waves<T, L>(), NT = 64 * W;
     __shared__ double acc[W][PF_LBM_MAX_BODIES][6];
+    __shared__ double bt[W][PF_LBM_MAX_BODIES][9];  // X, V, W of every body
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nbod = p.nb;
-    // each wave clears and fills only its own row of the sums: no barrier before the scan
+    // each wave clears and fills only its own row of the sums and reads its own copy of the body
+    // motion (loaded here, off the dependent chain of the scan): no barrier before the scan
     for (int k = lane; k < PF_LBM_MAX_BODIES * 6; k += 64) (&acc[wave][0][0])[k] = 0.0;
+    for (int k = lane; k < nbod * 9; k += 64) {
+        const BodyDev &B = bodies[k / 9];
+        const int c = k % 9;
+        bt[wave][k / 9][c] = c < 3 ? B.X[c] : (c < 6 ? B.V[c - 3] : B.W[c - 6]);
+    }
+    __builtin_amdgcn_wave_barrier();
     const BoxIter it(st->box[parity], p.nx, p.ny, p.nz);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
@@ -386,11 +394,11 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                 // c_i . u_w(x + c_i/2) = c_i . u_w(x) (the term c_i . (W x c_i)/2 vanishes) and
                 // (r + c_i/2) x s c_i = r x s c_i.  The wall term needs the node's rigid velocity
                 // only, and the torque is r x (sum of the link forces).
-                const BodyDev &B = bodies[b];
-                const double rx = mimg_r(x - B.X[0], nx, p.inv_n[0]), ry = mimg_r(y - B.X[1], ny, p.inv_n[1]),
-                             rz = mimg_r(z - B.X[2], nz, p.inv_n[2]);
-                const double u0x = B.V[0] + (B.W[1] * rz - B.W[2] * ry), u0y = B.V[1] + (B.W[2] * rx - B.W[0] * rz),
-                             u0z = B.V[2] + (B.W[0] * ry - B.W[1] * rx);
+                const double *BX = bt[wave][b], *BV = BX + 3, *BW = BX + 6;
+                const double rx = mimg_r(x - BX[0], nx, p.inv_n[0]), ry = mimg_r(y - BX[1], ny, p.inv_n[1]),
+                             rz = mimg_r(z - BX[2], nz, p.inv_n[2]);
+                const double u0x = BV[0] + (BW[1] * rz - BW[2] * ry), u0y = BV[1] + (BW[2] * rx - BW[0] * rz),
+                             u0z = BV[2] + (BW[0] * ry - BW[1] * rx);
                 double fx = 0.0, fy = 0.0, fz = 0.0;
                 sfor<L::Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;

@@ -287,10 +287,11 @@ struct ClassAcc {
     // Solid iff the fluid fraction 1 - sum phi is below the threshold, owner = argmax phi (lowest
     // index on ties; Sec. 3.2.2).  Updates the cell word (marks a change of side) and returns the
     // event-list entry + 1 of a node that changed side (bit 31: it became solid), else 0.
+    // old: the node's cell word, read by the caller ahead of the phase loads
     template <typename PT>
     __device__ __forceinline__ uint32_t node(const Prm<PT> &p, const BodyDev *__restrict__ bodies,
                                              cell_t *__restrict__ mask, int idx, const int *u, const int *c,
-                                             const double *out) {
+                                             const double *out, cell_t old) {
         const int nbod = p.nb;
         double sum = 0.0, best = -1.0;
         int arg = 0;
@@ -307,7 +308,6 @@ struct ClassAcc {
         }
         const bool solid = nbod > 0 && (1.0 - sum) < p.threshold;
         uint32_t event = 0;
-        const cell_t old = mask[idx];
         cell_t m = (old & C_NBMASK) | (solid ? solid_word(arg) : 0u);
         if (solid && !(old & C_SOLID)) {
             m |= C_F2S;
@@ -450,6 +450,7 @@ __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, Ste
             int u[3], c[3];
             it.cell(k, u, c);
             const int idx = c[0] + nx * (c[1] + ny * c[2]);
+            const cell_t old = mask[idx];  // issued with the phase loads
             double v[NBMAX], out[NBMAX];
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a) {
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, Ste
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a)
                 if (a < nbod) dst[(long long)a * Np + idx] = out[a];
-            event = acc.node(p, bodies, mask, idx, u, c, out);
+            event = acc.node(p, bodies, mask, idx, u, c, out, old);
         }
         append_events(st, evlist, evcap, event);
     }
