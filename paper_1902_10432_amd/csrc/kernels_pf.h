@@ -632,6 +632,58 @@ __device__ __forceinline__ int conversion_radius(const cell_t *mask, int x, int 
     return 0;
 }
 
+// The 3x3x3 neighbourhood of a node, its 27 cell words loaded in one round and kept as bit sets
+// (bit k for offset k = (dz + 1) 9 + (dy + 1) 3 + (dx + 1); 13 is the node itself), for the
+// conversion tests of the gather kernel, which otherwise wait for memory once per neighbour.
+struct Nbhd {
+    uint32_t f2s_bits = 0, fluid_bits = 0;  // "became solid" mark; not solid
+    cell_t centre;
+    int x, y, z, nx, ny, nz;
+    __device__ __forceinline__ Nbhd(const cell_t *mask, int x_, int y_, int z_, int nx_, int ny_, int nz_)
+        : x(x_), y(y_), z(z_), nx(nx_), ny(ny_), nz(nz_) {
+        cell_t w[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) w[k] = mask[index(k)];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            if (w[k] & C_F2S) f2s_bits |= 1u << k;
+            if (!(w[k] & C_SOLID)) fluid_bits |= 1u << k;
+        }
+        centre = w[13];
+    }
+    __device__ __forceinline__ uint32_t index(int k) const {
+        return (uint32_t)(wrapi(x + k % 3 - 1, nx) + nx * (wrapi(y + (k / 3) % 3 - 1, ny) + ny * wrapi(z + k / 9 - 1, nz)));
+    }
+    // does any of the 26 neighbours with a cell index below `below` carry the "became solid" mark
+    // (below = 0xFFFFFFFF: any neighbour)
+    __device__ __forceinline__ bool f2s(uint32_t below) const {
+        for (uint32_t b = f2s_bits & ~(1u << 13); b; b &= b - 1)
+            if (index(__ffs(b) - 1) < below) return true;
+        return false;
+    }
+    // conversion_radius of the centre node, counted from the bit set
+    __device__ __forceinline__ int conversion_radius(double RA, double &r2sel) const {
+        const double radii2[3] = {RA * RA, 2.0, 3.0};
+        for (int t = 0; t < 3; ++t) {
+            if (t > 0 && radii2[t] <= RA * RA + 1e-9) continue;
+            uint32_t within = 0;
+#pragma unroll
+            for (int k = 0; k < 27; ++k) {
+                const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+                const int d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 > 0 && !(d2 > radii2[t] + 1e-9)) within |= 1u << k;
+            }
+            const int c = __popc(fluid_bits & within);
+            if (c > 0) {
+                r2sel = radii2[t];
+                return c;
+            }
+        }
+        r2sel = 0.0;
+        return 0;
+    }
+};
+
 // Node conversion at one fluid node r (Sec. 3.2.2): the node gathers, from each neighbour that
 // just became solid and whose neighbourhood N_F contains it, f_eq(rho_n, u_n) / |N_F| with
 // rho_n, u_n = j_n / rho_n of the converted node's populations; a node that just became fluid
@@ -639,7 +691,8 @@ __device__ __forceinline__ int conversion_radius(const cell_t *mask, int x, int 
 // psi: the pseudopotential of this step (reference density of the FP16 form)
 template <typename S, class L>
 __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__ mask, S *f,
-                                const ArT<S> *__restrict__ psi, int x, int y, int z, int idx, cell_t m) {
+                                const ArT<S> *__restrict__ psi, int x, int y, int z, int idx, cell_t m,
+                                const Nbhd &nr) {
     using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
@@ -650,16 +703,14 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
         acc[I] = (m & C_S2F) ? T(0)
                              : pop_get<S>(f[(long long)I * Np + idx], Dir<decltype(I)::value, L>::template w<T>() * rr);
     });
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
+    for (int k = 0; k < 27; ++k) {
+                const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
                 const int d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 == 0) continue;
+                if (d2 == 0 || !((nr.f2s_bits >> k) & 1u)) continue;
                 const int sx = wrapi(x + dx, nx), sy = wrapi(y + dy, ny), sz = wrapi(z + dz, nz);
                 const int n = sx + nx * (sy + ny * sz);
-                if (!(mask[n] & C_F2S)) continue;
                 double r2;
-                const int cnt = conversion_radius(mask, sx, sy, sz, nx, ny, nz, p.R_A, r2);
+                const int cnt = Nbhd(mask, sx, sy, sz, nx, ny, nz).conversion_radius(p.R_A, r2);
                 if (cnt == 0 || d2 > r2 + 1e-9) continue;
                 T fs[L::Q];
                 const T rn = H ? ref_density(psi[n], p.rho0) : T(0);
@@ -688,19 +739,6 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
     });
 }
 
-// does any of the 26 neighbours of (x, y, z) with a cell index below `below` carry the "became
-// solid" mark (below = 0xFFFFFFFF: any neighbour)
-__device__ __forceinline__ bool f2s_neighbour(const cell_t *mask, int x, int y, int z, int nx, int ny, int nz,
-                                              uint32_t below) {
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy && !dz) continue;
-                const uint32_t n = (uint32_t)(wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz)));
-                if ((mask[n] & C_F2S) && n < below) return true;
-            }
-    return false;
-}
 
 // Node conversion, receiving side, after the reclassification of the step.  Usual case: no node
 // changed side and the kernel returns at once.  Otherwise the event list drives it: work item
@@ -727,8 +765,9 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
             const int idx = c[0] + nx * (c[1] + ny * c[2]);
             const cell_t m = mask[idx];
             if (m & C_SOLID) continue;
-            if (!(m & C_S2F) && !f2s_neighbour(mask, c[0], c[1], c[2], nx, ny, nz, 0xFFFFFFFFu)) continue;
-            gather_receiver<S, L>(p, mask, f, psi, c[0], c[1], c[2], idx, m);
+            const Nbhd nr(mask, c[0], c[1], c[2], nx, ny, nz);
+            if (!(m & C_S2F) && !nr.f2s(0xFFFFFFFFu)) continue;
+            gather_receiver<S, L>(p, mask, f, psi, c[0], c[1], c[2], idx, m, nr);
         }
         return;
     }
@@ -740,7 +779,7 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
         if (d == 13) {
             // a node that became fluid with no converted neighbour starts empty
             const cell_t m = mask[e];
-            if ((m & C_S2F) && !f2s_neighbour(mask, ex, ey, ez, nx, ny, nz, 0xFFFFFFFFu)) {
+            if ((m & C_S2F) && !Nbhd(mask, ex, ey, ez, nx, ny, nz).f2s(0xFFFFFFFFu)) {
                 const T re = sizeof(S) == 2 ? ref_density(psi[e], p.rho0) : T(0);
                 sfor<L::Q>([&](auto I) {
                     f[(long long)I * Np + e] = pop_put<S>(T(0), Dir<decltype(I)::value, L>::template w<T>() * re);
@@ -751,10 +790,11 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
         if (!(ent & 0x80000000u)) continue;  // only nodes that became solid hand on mass
         const int rx = wrapi(ex + d % 3 - 1, nx), ry = wrapi(ey + (d / 3) % 3 - 1, ny), rz = wrapi(ez + d / 9 - 1, nz);
         const int r = rx + nx * (ry + ny * rz);
-        const cell_t m = mask[r];
+        const Nbhd nr(mask, rx, ry, rz, nx, ny, nz);
+        const cell_t m = nr.centre;
         if (m & C_SOLID) continue;
-        if (f2s_neighbour(mask, rx, ry, rz, nx, ny, nz, e)) continue;  // a lower-index source handles r
-        gather_receiver<S, L>(p, mask, f, psi, rx, ry, rz, r, m);
+        if (nr.f2s(e)) continue;  // a lower-index source handles r
+        gather_receiver<S, L>(p, mask, f, psi, rx, ry, rz, r, m, nr);
     }
 }
 
