@@ -598,40 +598,6 @@ __device__ __forceinline__ T feq_dir(T rho, T ux, T uy, T uz) {
     return Dir<I, L>::template w<T>() * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
 }
 
-// number of fluid nodes (current mask) within squared radius r2 of node (x, y, z), over the 26
-// neighbours
-__device__ __forceinline__ int fluid_count(const cell_t *mask, int x, int y, int z, int nx, int ny, int nz, double r2) {
-    int cnt = 0;
-#pragma unroll 1
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 == 0 || d2 > r2 + 1e-9) continue;
-                const int n = wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz));
-                if (!(mask[n] & C_SOLID)) ++cnt;
-            }
-    return cnt;
-}
-
-// the neighbourhood N_F(x_n) of a node that became solid: fluid nodes within R_A, widened to
-// sqrt(2) and then sqrt(3) while it is empty.  Returns its squared radius and size (0 if empty).
-__device__ __forceinline__ int conversion_radius(const cell_t *mask, int x, int y, int z, int nx, int ny, int nz,
-                                                 double RA, double &r2sel) {
-    const double radii2[3] = {RA * RA, 2.0, 3.0};
-#pragma unroll 1
-    for (int t = 0; t < 3; ++t) {
-        if (t > 0 && radii2[t] <= RA * RA + 1e-9) continue;
-        const int c = fluid_count(mask, x, y, z, nx, ny, nz, radii2[t]);
-        if (c > 0) {
-            r2sel = radii2[t];
-            return c;
-        }
-    }
-    r2sel = 0.0;
-    return 0;
-}
-
 // The 3x3x3 neighbourhood of a node, its 27 cell words loaded in one round and kept as bit sets
 // (bit k for offset k = (dz + 1) 9 + (dy + 1) 3 + (dx + 1); 13 is the node itself), for the
 // conversion tests of the gather kernel, which otherwise wait for memory once per neighbour.
@@ -661,7 +627,8 @@ struct Nbhd {
             if (index(__ffs(b) - 1) < below) return true;
         return false;
     }
-    // conversion_radius of the centre node, counted from the bit set
+    // N_F of the centre node that became solid (Sec. 3.2.2): the fluid nodes within R_A, widened
+    // to sqrt 2 and then sqrt 3 while it is empty; returns its size (0 if empty) and squared radius
     __device__ __forceinline__ int conversion_radius(double RA, double &r2sel) const {
         const double radii2[3] = {RA * RA, 2.0, 3.0};
         for (int t = 0; t < 3; ++t) {
@@ -703,37 +670,39 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
         acc[I] = (m & C_S2F) ? T(0)
                              : pop_get<S>(f[(long long)I * Np + idx], Dir<decltype(I)::value, L>::template w<T>() * rr);
     });
-    for (int k = 0; k < 27; ++k) {
-                const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-                const int d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 == 0 || !((nr.f2s_bits >> k) & 1u)) continue;
-                const int sx = wrapi(x + dx, nx), sy = wrapi(y + dy, ny), sz = wrapi(z + dz, nz);
-                const int n = sx + nx * (sy + ny * sz);
-                double r2;
-                const int cnt = Nbhd(mask, sx, sy, sz, nx, ny, nz).conversion_radius(p.R_A, r2);
-                if (cnt == 0 || d2 > r2 + 1e-9) continue;
-                T fs[L::Q];
-                const T rn = H ? ref_density(psi[n], p.rho0) : T(0);
-                sfor<L::Q>([&](auto I) {
-                    fs[I] = pop_get<S>(f[(long long)I * Np + n], Dir<decltype(I)::value, L>::template w<T>() * rn);
-                });
-                T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
-                sfor<L::Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    rho += fs[i];
-                    jx += T(Dir<i, L>::x) * fs[i];
-                    jy += T(Dir<i, L>::y) * fs[i];
-                    jz += T(Dir<i, L>::z) * fs[i];
-                });
-                T vx = T(0), vy = T(0), vz = T(0);
-                if (rho > T(0)) {
-                    vx = jx / rho;
-                    vy = jy / rho;
-                    vz = jz / rho;
-                }
-                const T inv = T(1) / T(cnt);
-                sfor<L::Q>([&](auto I) { acc[I] += feq_dir<T, decltype(I)::value, L>(rho, vx, vy, vz) * inv; });
-            }
+    // sources in increasing offset order; the loop runs per lane over its own sources only (a loop
+    // over all 26 offsets would run, in a wave, over the union of its lanes' sources)
+    for (uint32_t srcs = nr.f2s_bits & ~(1u << 13); srcs; srcs &= srcs - 1) {
+        const int k = __ffs(srcs) - 1;
+        const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+        const int d2 = dx * dx + dy * dy + dz * dz;
+        const int sx = wrapi(x + dx, nx), sy = wrapi(y + dy, ny), sz = wrapi(z + dz, nz);
+        const int n = sx + nx * (sy + ny * sz);
+        double r2;
+        const int cnt = Nbhd(mask, sx, sy, sz, nx, ny, nz).conversion_radius(p.R_A, r2);
+        if (cnt == 0 || d2 > r2 + 1e-9) continue;
+        T fs[L::Q];
+        const T rn = H ? ref_density(psi[n], p.rho0) : T(0);
+        sfor<L::Q>([&](auto I) {
+            fs[I] = pop_get<S>(f[(long long)I * Np + n], Dir<decltype(I)::value, L>::template w<T>() * rn);
+        });
+        T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
+        sfor<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            rho += fs[i];
+            jx += T(Dir<i, L>::x) * fs[i];
+            jy += T(Dir<i, L>::y) * fs[i];
+            jz += T(Dir<i, L>::z) * fs[i];
+        });
+        T vx = T(0), vy = T(0), vz = T(0);
+        if (rho > T(0)) {
+            vx = jx / rho;
+            vy = jy / rho;
+            vz = jz / rho;
+        }
+        const T inv = T(1) / T(cnt);
+        sfor<L::Q>([&](auto I) { acc[I] += feq_dir<T, decltype(I)::value, L>(rho, vx, vy, vz) * inv; });
+    }
     sfor<L::Q>([&](auto I) {
         f[(long long)I * Np + idx] = pop_put<S>(acc[I], Dir<decltype(I)::value, L>::template w<T>() * rr);
     });
@@ -747,7 +716,7 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
 // and a node that became fluid with no converted neighbour is emptied.  When the list overflowed,
 // the whole box is scanned instead.
 template <typename S, class L>
-__global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parity, const StepState *st,
+__global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parity, StepState *st,
                                                         const cell_t *__restrict__ mask, S *f,
                                                         const ArT<S> *__restrict__ psi,
                                                         const uint32_t *__restrict__ evlist, uint32_t evcap) {
@@ -757,6 +726,9 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
     const int gtid = blockIdx.x * 256 + threadIdx.x, gstride = gridDim.x * 256;
+    // nodes that became solid with no fluid node in reach of R_A, sqrt 2 or sqrt 3: their content
+    // has no receiver and is lost (counted)
+    unsigned long long lost = 0;
     if (nev > evcap) {
         const BoxIter it(st->box[parity], nx, ny, nz);
         for (int k = gtid; k < it.vol; k += gstride) {
@@ -764,11 +736,16 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
             it.cell(k, u, c);
             const int idx = c[0] + nx * (c[1] + ny * c[2]);
             const cell_t m = mask[idx];
+            if (m & C_F2S) {
+                double r2;
+                if (Nbhd(mask, c[0], c[1], c[2], nx, ny, nz).conversion_radius(p.R_A, r2) == 0) ++lost;
+            }
             if (m & C_SOLID) continue;
             const Nbhd nr(mask, c[0], c[1], c[2], nx, ny, nz);
             if (!(m & C_S2F) && !nr.f2s(0xFFFFFFFFu)) continue;
             gather_receiver<S, L>(p, mask, f, psi, c[0], c[1], c[2], idx, m, nr);
         }
+        if (lost) atomicAdd(&st->n_lost, lost);  // rare
         return;
     }
     for (int j = gtid; j < (int)nev * 27; j += gstride) {
@@ -777,9 +754,11 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
         const uint32_t e = ent & 0x7FFFFFFFu;
         const int ex = (int)(e % (uint32_t)nx), ey = (int)((e / (uint32_t)nx) % (uint32_t)ny), ez = (int)(e / ((uint32_t)nx * ny));
         if (d == 13) {
+            const Nbhd ne(mask, ex, ey, ez, nx, ny, nz);
+            double r2;
+            if ((ent & 0x80000000u) && ne.conversion_radius(p.R_A, r2) == 0) ++lost;
             // a node that became fluid with no converted neighbour starts empty
-            const cell_t m = mask[e];
-            if ((m & C_S2F) && !Nbhd(mask, ex, ey, ez, nx, ny, nz).f2s(0xFFFFFFFFu)) {
+            if ((ne.centre & C_S2F) && !ne.f2s(0xFFFFFFFFu)) {
                 const T re = sizeof(S) == 2 ? ref_density(psi[e], p.rho0) : T(0);
                 sfor<L::Q>([&](auto I) {
                     f[(long long)I * Np + e] = pop_put<S>(T(0), Dir<decltype(I)::value, L>::template w<T>() * re);
@@ -796,26 +775,25 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
         if (nr.f2s(e)) continue;  // a lower-index source handles r
         gather_receiver<S, L>(p, mask, f, psi, rx, ry, rz, r, m, nr);
     }
+    if (lost) atomicAdd(&st->n_lost, lost);  // rare
 }
 
 // Upkeep of the cell words at one node: node conversion, source side (Sec. 3.2.2) -- a node that
-// became solid is emptied (its content was handed on by k_convert_gather) and counted when its
-// neighbourhood held no fluid node -- then the neighbour bits (bit i: the node in direction i is
-// solid) are recomputed and the event bits cleared.  Only solid bits of neighbours are read,
+// became solid is emptied (its content was handed on, or counted as lost, by k_convert_gather)
+// -- then the neighbour bits (bit i: the node in direction i is solid) are recomputed and the
+// event bits cleared.  Only solid bits of neighbours are read,
 // which this pass never changes, so repeated visits of one node write the same word.
 // empty: 0 never, 1 when the word carries the "became solid" mark (one visit per node), 2 always
 // (the caller knows the node became solid).
 template <typename S, class L>
 __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask, uint32_t *nbw, S *f, const ArT<S> *psi,
-                                             int x, int y, int z, uint32_t idx, int empty, unsigned long long &lost) {
+                                             int x, int y, int z, uint32_t idx, int empty) {
     using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     // runtime loops: this runs inside the pseudopotential pass, whose register budget it must
     // not raise (events are rare)
     const cell_t m = mask[idx];
     if (empty == 2 || (empty == 1 && (m & C_F2S))) {
-        double r2;
-        if (conversion_radius(mask, x, y, z, nx, ny, nz, p.R_A, r2) == 0) ++lost;
         const T rr = sizeof(S) == 2 ? ref_density(psi[idx], p.rho0) : T(0);
 #pragma unroll 1
         for (int i = 0; i < L::Q; ++i) {
@@ -847,14 +825,13 @@ __device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t 
                                             const uint32_t *evlist, uint32_t evcap, int full, int gtid,
                                             int gstride) {
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    unsigned long long lost = 0;
     if (full || nev > evcap) {
         const BoxIter it(box, nx, ny, nz);
         for (int k = gtid; k < it.vol; k += gstride) {
             int u[3], c[3];
             it.cell(k, u, c);
             refresh_node<S, L>(p, mask, nbw, f, psi, c[0], c[1], c[2], (uint32_t)(c[0] + nx * (c[1] + ny * c[2])),
-                               full ? 0 : 1, lost);
+                               full ? 0 : 1);
         }
     } else {
         // the event node and the Q - 1 nodes whose bit for it may change
@@ -867,10 +844,9 @@ __device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t 
             // node whose neighbour in direction i is e
             const int x = wrapi(ex - kCX[i], nx), y = wrapi(ey - kCY[i], ny), z = wrapi(ez - kCZ[i], nz);
             refresh_node<S, L>(p, mask, nbw, f, psi, x, y, z, (uint32_t)(x + nx * (y + ny * z)),
-                               (i == 0 && (ent & 0x80000000u)) ? 2 : 0, lost);
+                               (i == 0 && (ent & 0x80000000u)) ? 2 : 0);
         }
     }
-    if (lost) atomicAdd(&st->n_lost, lost);  // rare
 }
 
 // Every box node refreshed (initialisation: neighbour bits of the first cell words).
