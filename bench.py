@@ -131,7 +131,11 @@ def batched_sweep(args) -> int:
     tuned = None
     if args.autotune:
         tuned = [s.autotune(4) for s in sims]
+    # warm-up of both paths (each captures its graphs: step pairs for the batch, runs of 32 steps
+    # for an instance stepped alone)
     step_batch(sims, args.warmup)
+    for s in sims:
+        s.step(max(args.warmup, 32))
     torch.cuda.synchronize()
     # sequential: one instance at a time
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
