@@ -99,7 +99,12 @@ struct StepState {
     uint32_t step_no, pad;        // steps started (counted by the step-state publish)
     unsigned long long n_f2s, n_s2f, n_lost;
     float srad[PF_LBM_MAX_BODIES];  // largest distance of a solid node from its body's centre
-    double rep_mag[16];             // repulsion magnitude by squared node distance (r_c <= 4)
+    // offsets (dx, dy, dz) with 0 < |d|^2 < r_c^2 in scan order (dz, dy, dx increasing), packed as
+    // (dx + 8) | (dy + 8) << 8 | (dz + 8) << 16; at most 250 for r_c <= 4
+    int32_t n_rep, rep_off[256];
+    // force on p from a node q = p + d of another body (Sec. 3.1.2):
+    // -(d / |d|) e0 (n / r_c) |(|d| - r_c) / r_c|^(n - 1)
+    double rep_f[256][3];
 };
 
 // per-block results of the reclassification kernel, combined at the start of the next step

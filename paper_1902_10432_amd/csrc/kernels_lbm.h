@@ -298,7 +298,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
     const long long Np = p.Np;
     const bool rep = nbod > 1 && (p.flags & PF_LBM_REPULSION);
     const double rc = p.r_c;
-    const int R = rep ? (int)ceil(rc) : 0;
+    constexpr int RC = 16;  // repulsion offsets per round of loads
     for (int base = blockIdx.x * NT; base < it.vol; base += gridDim.x * NT) {
         const int k = base + tid;
         uint32_t touched = 0;
@@ -364,23 +364,16 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                     });
                 }
             } else if (rep) {
+                // a solid node of body b1 within r_c of the solid radius of a body b2 > b1 may
+                // have solid nodes of b2 within r_c: both bodies are marked, and the per-body
+                // pass below finds the pairs (a pair-free mark adds zeros)
                 b1 = owner_of(w0);
-                bool near = false;
                 for (int b2 = b1 + 1; b2 < nbod; ++b2) {
-                    const BodyDev &B = bodies[b2];
-                    const double rx = mimg_r(x - B.X[0], nx, p.inv_n[0]), ry = mimg_r(y - B.X[1], ny, p.inv_n[1]),
-                                 rz = mimg_r(z - B.X[2], nz, p.inv_n[2]);
-                    if (sqrt(rx * rx + ry * ry + rz * rz) < (double)st->srad[b2] + rc + 1e-3) near = true;
-                }
-                if (near) {
-                    for (int dz = -R; dz <= R; ++dz)
-                        for (int dy = -R; dy <= R; ++dy)
-                            for (int dx = -R; dx <= R; ++dx) {
-                                const int d2 = dx * dx + dy * dy + dz * dz;
-                                if (d2 == 0 || !((double)d2 < rc * rc)) continue;
-                                const cell_t mq = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
-                                if ((mq & C_SOLID) && owner_of(mq) > b1) touched |= (1u << b1) | (1u << owner_of(mq));
-                            }
+                    const double *BX = bt[wave][b2];
+                    const double rx = mimg_r(x - BX[0], nx, p.inv_n[0]), ry = mimg_r(y - BX[1], ny, p.inv_n[1]),
+                                 rz = mimg_r(z - BX[2], nz, p.inv_n[2]);
+                    if (sqrt(rx * rx + ry * ry + rz * rz) < (double)st->srad[b2] + rc + 1e-3)
+                        touched |= (1u << b1) | (1u << b2);
                 }
             }
         }
@@ -428,37 +421,52 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                 v[4] = rz * fx - rx * fz;
                 v[5] = rx * fy - ry * fx;
             } else if (touched & (1u << b)) {
-                for (int dz = -R; dz <= R; ++dz)
-                    for (int dy = -R; dy <= R; ++dy)
-                        for (int dx = -R; dx <= R; ++dx) {
-                            const int d2 = dx * dx + dy * dy + dz * dz;
-                            if (d2 == 0 || !((double)d2 < rc * rc)) continue;
-                            const cell_t mq = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
-                            if (!(mq & C_SOLID)) continue;
-                            const int b2 = owner_of(mq);
-                            if (b2 <= b1 || (b != b1 && b != b2)) continue;
-                            const double r = sqrt((double)d2);
-                            const double mag = st->rep_mag[d2];
-                            // force on b1 at p, directed from q to p
-                            double fx = -dx / r * mag, fy = -dy / r * mag, fz = -dz / r * mag;
-                            double ax = x, ay = y, az = z;
-                            if (b == b2) {
-                                fx = -fx;
-                                fy = -fy;
-                                fz = -fz;
-                                ax = x + dx;
-                                ay = y + dy;
-                                az = z + dz;
-                            }
-                            const BodyDev &B = bodies[b];
-                            const double rx = mimg(ax - B.X[0], nx), ry = mimg(ay - B.X[1], ny), rz = mimg(az - B.X[2], nz);
-                            v[0] += fx;
-                            v[1] += fy;
-                            v[2] += fz;
-                            v[3] += ry * fz - rz * fy;
-                            v[4] += rz * fx - rx * fz;
-                            v[5] += rx * fy - ry * fx;
+                // repulsion between this solid node p of body b1 and the solid nodes q = p + d of
+                // bodies above b1: on b1 at p (b == b1), or the reaction on b at q (b != b1).  With
+                // r the offset of p from the centre of b, the torque is r x (sum f) for b1 and
+                // r x (sum f) + sum d x f for the reaction, so each pair costs a few additions.
+                const bool react = b != b1;
+                double sfx = 0.0, sfy = 0.0, sfz = 0.0, tdx = 0.0, tdy = 0.0, tdz = 0.0;
+                const int nrep = st->n_rep;
+                for (int j0 = 0; j0 < nrep; j0 += RC) {
+                    cell_t mqs[RC];
+#pragma unroll
+                    for (int j = 0; j < RC; ++j) {
+                        const int o = st->rep_off[j0 + j < nrep ? j0 + j : j0];
+                        const int dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
+                        mqs[j] = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
+                    }
+#pragma unroll
+                    for (int j = 0; j < RC; ++j) {
+                        if (j0 + j >= nrep) break;
+                        const cell_t mq = mqs[j];
+                        if (!(mq & C_SOLID)) continue;
+                        const int b2 = owner_of(mq);
+                        if (b2 <= b1 || (react && b != b2)) continue;
+                        // force on b1 at p, directed from q to p; its opposite on b2 at q
+                        const double sg = react ? -1.0 : 1.0;
+                        const double fx = sg * st->rep_f[j0 + j][0], fy = sg * st->rep_f[j0 + j][1],
+                                     fz = sg * st->rep_f[j0 + j][2];
+                        sfx += fx;
+                        sfy += fy;
+                        sfz += fz;
+                        if (react) {
+                            const int o = st->rep_off[j0 + j];
+                            const double dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
+                            tdx += dy * fz - dz * fy;
+                            tdy += dz * fx - dx * fz;
+                            tdz += dx * fy - dy * fx;
                         }
+                    }
+                }
+                const double *BX = bt[wave][b];
+                const double rx = mimg(x - BX[0], nx), ry = mimg(y - BX[1], ny), rz = mimg(z - BX[2], nz);
+                v[0] = sfx;
+                v[1] = sfy;
+                v[2] = sfz;
+                v[3] = ry * sfz - rz * sfy + tdx;
+                v[4] = rz * sfx - rx * sfz + tdy;
+                v[5] = rx * sfy - ry * sfx + tdz;
             }
 #pragma unroll
             for (int c = 0; c < 6; ++c) {

@@ -803,10 +803,20 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
     }
     uint32_t bits = 0;
     {
+        // the neighbours' words in rounds of nine loads (one latency per round, few registers)
         const Nbr nb(x, y, z, nx, ny, nz);
 #pragma unroll 1
-        for (int i = 1; i < L::Q; ++i)
-            if (mask[(int)idx + nb.off_rt(i)] & C_SOLID) bits |= 1u << i;
+        for (int i0 = 1; i0 < L::Q; i0 += 9) {
+            cell_t w[9];
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                const int i = i0 + j < L::Q ? i0 + j : 0;  // direction 0: the node itself, ignored
+                w[j] = mask[(int)idx + nb.off_rt(i)];
+            }
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+                if (i0 + j < L::Q && (w[j] & C_SOLID)) bits |= 1u << (i0 + j);
+        }
     }
     // D3Q19: the bits in the cell word; D3Q27: in the neighbour-bit word
     const cell_t mn = (m & ~(C_F2S | C_S2F | C_NBMASK)) | (L::kBits ? bits : 0u);

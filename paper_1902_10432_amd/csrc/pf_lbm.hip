@@ -555,11 +555,23 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     StepState st0;
     std::memset(&st0, 0, sizeof st0);
     for (int d = 0; d < 6; ++d) st0.box[0][d] = st0.box[1][d] = box[d];
-    // Sec. 3.1.2: e0 (n / r_c) |(r - r_c) / r_c|^(n - 1) for node distances 0 < r < r_c
-    for (int d2 = 1; d2 < 16; ++d2) {
-        const double r = std::sqrt((double)d2), rc = h->cfg.r_c;
-        st0.rep_mag[d2] = r < rc ? h->cfg.e0 * (h->cfg.n_exp / rc) * std::pow(std::fabs((r - rc) / rc), h->cfg.n_exp - 1.0)
-                                 : 0.0;
+    if ((h->cfg.flags & PF_LBM_REPULSION) && h->cfg.r_c > 0.0 && h->cfg.r_c <= 4.0) {
+        const double rc = h->cfg.r_c;
+        const int R = (int)std::ceil(rc);
+        for (int dz = -R; dz <= R; ++dz)
+            for (int dy = -R; dy <= R; ++dy)
+                for (int dx = -R; dx <= R; ++dx) {
+                    const int d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 == 0 || !((double)d2 < rc * rc)) continue;
+                    // Sec. 3.1.2: e0 (n / r_c) |(r - r_c) / r_c|^(n - 1) at node distance r < r_c
+                    const double r = std::sqrt((double)d2);
+                    const double mag =
+                        r < rc ? h->cfg.e0 * (h->cfg.n_exp / rc) * std::pow(std::fabs((r - rc) / rc), h->cfg.n_exp - 1.0) : 0.0;
+                    st0.rep_f[st0.n_rep][0] = -dx / r * mag;
+                    st0.rep_f[st0.n_rep][1] = -dy / r * mag;
+                    st0.rep_f[st0.n_rep][2] = -dz / r * mag;
+                    st0.rep_off[st0.n_rep++] = (dx + 8) | (dy + 8) << 8 | (dz + 8) << 16;
+                }
     }
     int rc = h->q == 27 ? (h->prec == PF_LBM_FP64   ? init_device<double, D3Q27>(h, bodies, rho0, phi0, bd, st0)
                            : h->prec == PF_LBM_FP32 ? init_device<float, D3Q27>(h, bodies, rho0, phi0, bd, st0)
