@@ -230,24 +230,74 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     }
     const NbrU ne(x, y, z, nx, ny, nz, 1);
     T drho = T(0);
-    sfor<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (i > 0) {
-            if (!(solid_dirs & (1u << i))) {
-                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
-            } else {
-                // reflected into direction opp(i) with g = -2 rho w_i (c_i . u_w) / c_s^2, u_w at
-                // the link midpoint x + c_i / 2
-                const BodyDev &Bd = bodies[owner_of(mask[ne.template at<i>(idx)])];
-                double uwx, uwy, uwz;
-                wall_velocity(p, Bd, x + 0.5 * Dir<i, L>::x, y + 0.5 * Dir<i, L>::y, z + 0.5 * Dir<i, L>::z, uwx, uwy, uwz);
-                const double cuw = Dir<i, L>::x * uwx + Dir<i, L>::y * uwy + Dir<i, L>::z * uwz;
-                const T gw = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
-                stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
-                drho += gw;
+    if constexpr (L::kBits && sizeof(S) != 2) {
+        // D3Q19, FP32 and FP64 populations: the owners of the solid neighbours come from one
+        // round of gathers, then the reflections run body by body (wave-uniform loop) with the
+        // body read once.  c_i . u_w at the link midpoint x + c_i/2 equals c_i . u_w(x), as
+        // c_i . (omega x c_i) = 0, so the node's rigid velocity serves every link.  (Loads inside
+        // per-link branches wait for memory once per link; this path keeps the interface waves
+        // from trailing the pass.  The FP16-storage form keeps the per-link path: its encoded
+        // reflections are sensitive to the rounding of the wall term.)
+        uint32_t own[(L::Q + 7) / 8] = {};
+        uint32_t touched = 0;
+        sfor<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0) {
+                const cell_t mw = ldb(mask, ne.template at<i>(idx) * 4u);
+                if (!(solid_dirs & (1u << i))) {
+                    stb(fout + (long long)i * Np, ns.template at<i>(is),
+                        pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
+                } else {
+                    const uint32_t o = (uint32_t)owner_of(mw);
+                    own[i >> 3] |= o << (4 * (i & 7));
+                    touched |= 1u << o;
+                }
             }
+        });
+        for (int b = 0; b < p.nb; ++b) {
+            if (!__ballot((touched >> b) & 1u)) continue;
+            if (!((touched >> b) & 1u)) continue;
+            const BodyDev &Bd = bodies[b];
+            const double rx = mimg_r(x - Bd.X[0], nx, p.inv_n[0]), ry = mimg_r(y - Bd.X[1], ny, p.inv_n[1]),
+                         rz = mimg_r(z - Bd.X[2], nz, p.inv_n[2]);
+            const double u0x = Bd.V[0] + (Bd.W[1] * rz - Bd.W[2] * ry), u0y = Bd.V[1] + (Bd.W[2] * rx - Bd.W[0] * rz),
+                         u0z = Bd.V[2] + (Bd.W[0] * ry - Bd.W[1] * rx);
+            sfor<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (i > 0) {
+                    if ((solid_dirs & (1u << i)) && ((own[i >> 3] >> (4 * (i & 7))) & 15u) == (uint32_t)b) {
+                        double cuw = 0.0;
+                        if constexpr (Dir<i, L>::x != 0) cuw += Dir<i, L>::x * u0x;
+                        if constexpr (Dir<i, L>::y != 0) cuw += Dir<i, L>::y * u0y;
+                        if constexpr (Dir<i, L>::z != 0) cuw += Dir<i, L>::z * u0z;
+                        const T gw = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
+                        stb(fout + (long long)Dir<i, L>::opp * Np, is,
+                            pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
+                        drho += gw;
+                    }
+                }
+            });
         }
-    });
+    } else {
+        sfor<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0) {
+                if (!(solid_dirs & (1u << i))) {
+                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
+                } else {
+                    // reflected into direction opp(i) with g = -2 rho w_i (c_i . u_w) / c_s^2, u_w at
+                    // the link midpoint x + c_i / 2
+                    const BodyDev &Bd = bodies[owner_of(mask[ne.template at<i>(idx)])];
+                    double uwx, uwy, uwz;
+                    wall_velocity(p, Bd, x + 0.5 * Dir<i, L>::x, y + 0.5 * Dir<i, L>::y, z + 0.5 * Dir<i, L>::z, uwx, uwy, uwz);
+                    const double cuw = Dir<i, L>::x * uwx + Dir<i, L>::y * uwy + Dir<i, L>::z * uwz;
+                    const T gw = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
+                    stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
+                    drho += gw;
+                }
+            }
+        });
+    }
     stb(fout, is, pop_put<S>(f[0] - drho, Dir<0, L>::template w<T>() * rown));
 }
 
