@@ -828,9 +828,9 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
 // Closing work of a step's node conversions, run after the conversion gather: with full != 0
 // (initialisation) or an overflowed event list, every node of the box is refreshed; otherwise
 // only the nodes whose words can have changed: each event node (emptied if it became solid) and
-// the 18 nodes that have it as a neighbour.  Threads gtid (of gstride) take the work in turn.
+// the Q - 1 nodes that have it as a neighbour.  Threads gtid (of gstride) take the work in turn.
 template <typename S, class L>
-__device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t *box, uint32_t nev, StepState *st,
+__device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t *box, uint32_t nev,
                                             cell_t *mask, uint32_t *nbw, S *f, const ArT<S> *psi,
                                             const uint32_t *evlist, uint32_t evcap, int full, int gtid,
                                             int gstride) {
@@ -863,7 +863,7 @@ __device__ __forceinline__ void post_events(const Prm<ArT<S>> &p, const int32_t 
 template <typename S, class L>
 __global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepState *st, cell_t *__restrict__ mask,
                                               uint32_t *nbw, S *f, const ArT<S> *__restrict__ psi) {
-    post_events<S, L>(p, st->box[parity], 0u, st, mask, nbw, f, psi, nullptr, 0u, 1, blockIdx.x * 256 + threadIdx.x,
+    post_events<S, L>(p, st->box[parity], 0u, mask, nbw, f, psi, nullptr, 0u, 1, blockIdx.x * 256 + threadIdx.x,
                       gridDim.x * 256);
 }
 
@@ -884,7 +884,7 @@ __global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, int parity, StepStat
     using T = ArT<S>;
     const uint32_t nev = st ? st->n_events : 0u;
     if (nev)
-        post_events<S, L>(p, st->box[parity ^ 1], nev, st, mask, nbw, f, psi_ref, evlist, evcap, 0,
+        post_events<S, L>(p, st->box[parity ^ 1], nev, mask, nbw, f, psi_ref, evlist, evcap, 0,
                           blockIdx.x * (int)blockDim.x + threadIdx.x, gridDim.x * (int)blockDim.x);
     const int idx = xcd_block(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
     if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed

@@ -697,8 +697,6 @@ int pf_lbm_fields(pf_lbm *h, int32_t which, void *dst, int32_t dst_dtype) {
     if (!ok) return fail(h, PF_LBM_EINVAL, "unknown field %d", which);
     if (dst_dtype != PF_LBM_DST_F64 && dst_dtype != PF_LBM_DST_F32) return fail(h, PF_LBM_EINVAL, "bad dst dtype");
     const int par = (int)(h->steps & 1);
-    const dim3 g(std::max(1, std::min(h->dense_blocks, 65535))), b(256);
-    const cell_t *mask = (const cell_t *)(h->ws + h->L.mask);
     if (h->q == 27) {
         if (h->prec == PF_LBM_FP64)
             launch_fields<double, D3Q27>(h, which, par, dst, dst_dtype);
