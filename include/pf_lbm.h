@@ -101,6 +101,11 @@ typedef struct {
     double R_A;             /* redistribution radius of node conversion, 1 <= R_A <= sqrt(3)     */
                             /* (Sec. 3.2.2)                                                        */
     double fext[3];         /* uniform external force density on the fluid (0 in the paper)       */
+    double phi_floor;       /* resolution of "phi > 0" in the present-phase and interface sets of */
+                            /* the kinetics and the volume term (Sec. 3.3), in [0, 0.5): values   */
+                            /* at or below it count as absent and the kinetics flushes them to 0; */
+                            /* 2^-53 (FP64 unit round-off) is the value used by the workloads,    */
+                            /* 0 the literal set                                                  */
 } pf_lbm_config;
 
 typedef struct {

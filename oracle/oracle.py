@@ -31,6 +31,8 @@ class _Config(C.Structure):
         ("fext", C.c_double * 3),
         ("kinetics", C.c_int32), ("motion", C.c_int32), ("repulsion", C.c_int32),
         ("lattice", C.c_int32),
+        ("phi_floor", C.c_double),
+        ("volume_after_advection", C.c_int32),
     ]
 
 
@@ -131,6 +133,8 @@ class Oracle:
             cfg.fext[d] = float(params["fext"][d])
         cfg.kinetics, cfg.motion, cfg.repulsion = int(params["kinetics"]), int(params["motion"]), int(params["repulsion"])
         cfg.lattice = int(params.get("lattice", 19))
+        cfg.phi_floor = float(params["phi_floor"])
+        cfg.volume_after_advection = int(params.get("volume_after_advection", 0))
         barr = (_Body * max(nb, 1))()
         for i, b in enumerate(bodies):
             barr[i].mass_density = float(b["mass_density"])

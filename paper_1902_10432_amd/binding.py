@@ -56,6 +56,7 @@ class PfLbmConfig(C.Structure):
         ("r_c", C.c_double), ("n_exp", C.c_double), ("e0", C.c_double),
         ("R_A", C.c_double),
         ("fext", C.c_double * 3),
+        ("phi_floor", C.c_double),
     ]
 
 

@@ -113,7 +113,7 @@ struct ClassifyPart {
     uint32_t f2s, s2f;              // nodes that became solid / fluid
     float srad[PF_LBM_MAX_BODIES];  // per-body largest solid-node distance from the centre
     double vol[PF_LBM_MAX_BODIES];  // per-body sum of phi
-    uint32_t icnt[PF_LBM_MAX_BODIES];  // per-body count of interface nodes floor < phi < 1
+    uint32_t icnt[PF_LBM_MAX_BODIES];  // per-body count of interface nodes phi_floor < phi < 1
 };
 
 // Deterministic sum of v[0..n) by one wave: lane l accumulates v[l + 64 m] into four
@@ -231,6 +231,7 @@ struct Prm {
     T fext[3];
     int flags;       // PF_LBM_* step flags
     double threshold, mobility, eta, r_c, n_exp, e0, R_A;
+    double phi_floor; // phase values at or below it count as absent (Sec. 3.3)
     double inv_n[3]; // 1 / nx, 1 / ny, 1 / nz
 };
 
@@ -302,7 +303,7 @@ __device__ __forceinline__ int wrap2(int i, int n) {
 //    and count the step;
 //  * per body (waves 1.., round robin; wave 0 alone in a one-wave block): the solid radius
 //    (bounds the repulsion search) and the volume
-//    driving term h_a = (4 eta / pi^2) (V_ref - sum phi_a) / #{floor < phi_a < 1} (Sec. 3.3; 0
+//    driving term h_a = (4 eta / pi^2) (V_ref - sum phi_a) / #{phi_floor < phi_a < 1} (Sec. 3.3; 0
 //    without interface nodes), into the body table;
 // and clear the event count for this step's reclassification.  Each lane sums its parts with four
 // independent accumulators, then a fixed xor-shuffle tree combines the lanes.

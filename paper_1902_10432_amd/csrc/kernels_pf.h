@@ -9,11 +9,6 @@
 
 namespace pfl {
 
-// Phase values below this floor count as absent: the kinetics flushes them to zero and the
-// interface count of the volume term ignores them, so round-off-level tails that advection
-// smears ahead of a body neither activate a phase at a node nor enter the volume term.
-constexpr double PHI_FLOOR = 1e-10;
-
 // monotonized-central slope (van Leer 1977)
 template <typename T>
 __device__ __forceinline__ T mc_slope(T dl, T dr) {
@@ -178,18 +173,18 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
 
 // Multi-phase-field kinetics at one node (Sec. 3.3), explicit Euler: v[a] are the advected solid
 // phases at the node, nbv(e, a) the value of phase a at face neighbour e (0..5); phase 0 = fluid
-// = 1 - sum of solids.  For nodes where at least two phases are active (above the floor at the
-// node or a face neighbour):
+// = 1 - sum of solids.  For nodes where at least two phases are active (above floor_, the
+// resolution of "phi > 0", at the node or a face neighbour):
 //   dphi_a/dt = sum_{b active, b != a} (M/N) ( sigma_ab (I_a - I_b)
 //               + sum_{g active, g != a, b} (sigma_bg - sigma_ag) I_g + pi^2/(4 eta) (h_a - h_b) ),
 // I = lap(phi) + (pi^2/eta^2) phi with the 7-point Laplacian, h_fluid = 0 and h_a the volume
-// driving term (set at the start of the step from the phase fields before advection, which
-// leaves the volumes unchanged); then each solid phase is clipped to [0, 1] (values below the
-// floor to 0) and the solids are rescaled if their sum exceeds 1.  sg: (NBMAX+1)^2 interface
+// driving term (evaluated from the phase fields at time t, the level the explicit step starts
+// from, before the advection sweeps); then each solid phase is clipped to [0, 1] (values below
+// floor_ to 0) and the solids are rescaled if their sum exceeds 1.  sg: (NBMAX+1)^2 interface
 // energies, hh: driving terms with hh[0] = 0.
 template <int NBMAX, typename NbrF>
 __device__ __forceinline__ void kinetics_node(const double *v, NbrF nbv, int nbod, const double *sg, const double *hh,
-                                              double mu, double vterm, double M, double *out) {
+                                              double mu, double vterm, double M, double floor_, double *out) {
     using T = double;
     constexpr int NP = NBMAX + 1;
     T v0[NP];
@@ -205,7 +200,7 @@ __device__ __forceinline__ void kinetics_node(const double *v, NbrF nbv, int nbo
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         lap[q] = T(-6) * v0[q];
-        on[q] = v0[q] > T(PHI_FLOOR);
+        on[q] = v0[q] > floor_;
     }
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
@@ -215,11 +210,11 @@ __device__ __forceinline__ void kinetics_node(const double *v, NbrF nbv, int nbo
             const T w = nbv(e, a);
             s += w;
             lap[a + 1] += w;
-            on[a + 1] = on[a + 1] || w > T(PHI_FLOOR);
+            on[a + 1] = on[a + 1] || w > floor_;
         }
         const T vf = T(1) - s;
         lap[0] += vf;
-        on[0] = on[0] || vf > T(PHI_FLOOR);
+        on[0] = on[0] || vf > floor_;
     }
     int na = 0;
     T I[NP];
@@ -249,7 +244,7 @@ __device__ __forceinline__ void kinetics_node(const double *v, NbrF nbv, int nbo
             }
             nv = v0[a] + rate;
         }
-        nv = nv < T(PHI_FLOOR) ? T(0) : (nv > T(1) ? T(1) : nv);
+        nv = nv < floor_ ? T(0) : (nv > T(1) ? T(1) : nv);
         out[a - 1] = nv;
         tot += nv;
     }
@@ -261,7 +256,7 @@ __device__ __forceinline__ void kinetics_node(const double *v, NbrF nbv, int nbo
 
 // Reclassification of the nodes of a phase update and the per-block results the next step
 // publishes (publish_step_state): support bounds (unwrapped coordinates), conversion counts,
-// per-body solid radius, sum of phi and count of interface nodes floor < phi < 1.
+// per-body solid radius, sum of phi and count of interface nodes phi_floor < phi < 1.
 template <int NBMAX>
 struct ClassAcc {
     int lo[3], hi[3];
@@ -304,7 +299,7 @@ struct ClassAcc {
                 arg = a;
             }
             vol[a] += out[a];
-            icnt[a] += (out[a] > PHI_FLOOR && out[a] < 1.0) ? 1u : 0u;
+            icnt[a] += (out[a] > p.phi_floor && out[a] < 1.0) ? 1u : 0u;
         }
         const bool solid = nbod > 0 && (1.0 - sum) < p.threshold;
         uint32_t event = 0;
@@ -467,7 +462,7 @@ __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, Ste
                     [&](int e, int a) {
                         return (a < nbod && ins[e]) ? src[(long long)a * Np + idx + offs[e]] : 0.0;
                     },
-                    nbod, sg, hh, mu, vterm, M, out);
+                    nbod, sg, hh, mu, vterm, M, p.phi_floor, out);
             }
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a)
@@ -482,7 +477,7 @@ __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, Ste
 // Classification of the initial phase fields (Sec. 3.2.2): solid iff the fluid fraction
 // 1 - sum phi is below the threshold, owner = argmax phi (lowest index on ties).  Each block
 // writes to cpart[block] its support bounds (unwrapped coordinates), per-body solid radius, sum
-// of phi and count of interface nodes floor < phi < 1, which the first step publishes.  (During
+// of phi and count of interface nodes phi_floor < phi < 1, which the first step publishes.  (During
 // the run the phase-update kernel classifies.)
 template <typename PT>
 __global__ __launch_bounds__(256) void k_classify_init(Prm<PT> p, int parity, const StepState *st,
@@ -528,7 +523,7 @@ __global__ __launch_bounds__(256) void k_classify_init(Prm<PT> p, int parity, co
                 arg = a;
             }
             const double vs = wave_sum(v);
-            const int ic = wave_sum((v > PHI_FLOOR && v < 1.0) ? 1 : 0);
+            const int ic = wave_sum((v > p.phi_floor && v < 1.0) ? 1 : 0);
             if (lane == 0) {
                 sv[wave][a] += vs;
                 si[wave][a] += (uint32_t)ic;

@@ -244,6 +244,7 @@ Prm<T> make_prm(const pf_lbm *h) {
     p.n_exp = h->cfg.n_exp;
     p.e0 = h->cfg.e0;
     p.R_A = h->cfg.R_A;
+    p.phi_floor = h->cfg.phi_floor;
     p.inv_n[0] = 1.0 / h->cfg.nx;
     p.inv_n[1] = 1.0 / h->cfg.ny;
     p.inv_n[2] = 1.0 / h->cfg.nz;
@@ -454,6 +455,7 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
         return fail(nullptr, PF_LBM_EUNSUPPORTED, "R_A must lie in [1, sqrt(3)]");
     if ((cfg->flags & PF_LBM_REPULSION) && !(cfg->r_c > 0.0 && cfg->r_c <= 4.0))
         return fail(nullptr, PF_LBM_EUNSUPPORTED, "r_c must lie in (0, 4]");
+    if (!(cfg->phi_floor >= 0.0 && cfg->phi_floor < 0.5)) return fail(nullptr, PF_LBM_EINVAL, "phi_floor must lie in [0, 0.5)");
     if (!(cfg->solid_threshold > 0.0 && cfg->solid_threshold < 1.0))
         return fail(nullptr, PF_LBM_EINVAL, "solid_threshold must lie in (0, 1)");
     if (n_bodies > 0 && (!bodies || !phi0)) return fail(nullptr, PF_LBM_EINVAL, "bodies and phi0 are required");

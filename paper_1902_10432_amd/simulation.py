@@ -37,6 +37,7 @@ def make_config(params: dict, n_bodies: int, precision: str):
     cfg.R_A = params["RA"]
     for d in range(3):
         cfg.fext[d] = float(params["fext"][d])
+    cfg.phi_floor = float(params["phi_floor"])
     return cfg, sig
 
 

@@ -16,6 +16,11 @@ from __future__ import annotations
 
 import numpy as np
 
+# Resolution of "phi > 0" in the present-phase and interface sets of Sec. 3.3 (a reading): phase
+# values at or below the unit round-off of FP64, 2^-53, cannot change the fluid fraction
+# 1 - sum phi and count as absent.
+PHI_FLOOR = 2.0 ** -53
+
 
 def sigma_matrix(nb: int, sigma_sf: float = 1.0, sigma_ss: float = 0.5) -> np.ndarray:
     """(nb+1) x (nb+1) interface energies, phase 0 = fluid, zero diagonal."""
@@ -38,6 +43,7 @@ def paper_params(nx: int, ny: int, nz: int, nb: int) -> dict:
         "fext": (0.0, 0.0, 0.0),
         "kinetics": 1, "motion": 1, "repulsion": 1,
         "lattice": 19,
+        "phi_floor": PHI_FLOOR,
     }
 
 

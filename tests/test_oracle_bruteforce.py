@@ -20,7 +20,6 @@ from pflbm_inputs import default_params
 
 CS2 = 1.0 / 3.0
 PI = math.pi
-FLOOR = 1e-10
 
 
 def d3q19():
@@ -62,6 +61,7 @@ def mimg(d, L):
 class Brute:
     def __init__(self, p, bodies, rho0, phi0):
         self.p = p
+        self.floor = p["phi_floor"]  # resolution of "phi > 0" (Sec. 3.3)
         self.nz, self.ny, self.nx = rho0.shape
         self.n = np.array([self.nx, self.ny, self.nz])
         self.c, self.w, self.opp = d3q27() if p.get("lattice", 19) == 27 else d3q19()
@@ -207,7 +207,7 @@ class Brute:
         # volume terms from the phase fields before advection
         h = np.zeros(self.nb + 1)
         for a in range(self.nb):
-            cnt = ((self.phi[a] > FLOOR) & (self.phi[a] < 1)).sum()
+            cnt = ((self.phi[a] > self.floor) & (self.phi[a] < 1)).sum()
             h[a + 1] = (4 * p["eta"] / PI ** 2) * (self.Vref[a] - self.phi[a].sum()) / cnt if cnt else 0.0
         # advection: split conservative sweeps along x, y, z with MC-limited fluxes
         for a in range(self.nb):
@@ -235,7 +235,7 @@ class Brute:
                 z, y, x = idx
                 nbrs = [self.wrap(x + dx, y + dy, z + dz) for dx, dy, dz in
                         ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))]
-                act = [q for q in range(self.nb + 1) if allp[q][idx] > FLOOR or any(allp[q][n] > FLOOR for n in nbrs)]
+                act = [q for q in range(self.nb + 1) if allp[q][idx] > self.floor or any(allp[q][n] > self.floor for n in nbrs)]
                 I = {q: sum(allp[q][n] for n in nbrs) - 6 * allp[q][idx] + mu * allp[q][idx] for q in act}
                 if len(act) < 2:
                     continue
@@ -250,7 +250,7 @@ class Brute:
                         t += sum((sig[b, g] - sig[a, g]) * I[g] for g in act if g not in (a, b))
                         rate += p["mobility"] / len(act) * t
                     new[a - 1][idx] += rate
-            new = np.where(new < FLOOR, 0.0, np.minimum(new, 1.0))
+            new = np.where(new < self.floor, 0.0, np.minimum(new, 1.0))
             s = new.sum(0)
             self.phi = np.where(s > 1, new / np.where(s > 1, s, 1), new)
         # reclassification and node conversion, pushed from each converted node
