@@ -1,15 +1,17 @@
 #!/usr/bin/env python
 """Throughput of the coupled phase-field / lattice-Boltzmann step on one MI355X.
 
-Default workload: two spheres (R = 20, nominal surface gap 4) joined by a liquid bridge of 2 % of
-one sphere's volume, 30 degree wetting, 128^3 D3Q19, FP32 populations and phase fields, rigid-body
-motion and phase-field kinetics on.  A step is the whole coupled step (every kernel).  Inputs are
-resident in HBM before the timed region.
+Default workload: four spheres (R = 24) at the vertices of a regular tetrahedron around a central
+liquid drop of 5 % liquid fraction, seeded 1e-3 perturbations of the phase fields, 30 degree
+wetting, 256^3 D3Q19, tau = 1.1, FP32 populations, rigid-body motion and phase-field kinetics on;
+beside it the same workload with FP16 population storage.  A step is the whole coupled step
+(every kernel).  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: MLUPS (all nodes x steps / s), the step's algorithmic fraction of HBM peak,
 the dominant kernel's roofline (algorithmic bytes per launch over its mean launch time measured
 with HIP events on the library's stream), and the FP64 CPU oracle timed on the host on a bounded
-sample of the same workload.
+sample of the same workload.  --oracle-timing instead times the oracle alone on the three
+single-grid workloads, on all host cores and on one thread.
 """
 from __future__ import annotations
 
@@ -112,6 +114,44 @@ def cpu_baseline(w, seconds: float) -> dict:
     return {"value": round(w.cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{n} steps of the same {w.shape[2]}x{w.shape[1]}x{w.shape[0]} workload in FP64 "
                       f"after 1 warm-up step ({dt:.1f} s)"}
+
+
+def oracle_timing() -> int:
+    """The FP64 oracle on the host: MLUPS on all cores (OpenMP threads) and on one thread, for the
+    32^3 plates bridge (200 steps), the 128^3 two-sphere bridge and the 256^3 four-sphere workload
+    (short slices after one untimed warm-up step, which also touches the oracle's memory).  One
+    JSON line per run."""
+    import platform
+
+    import oracle
+    from pflbm_inputs import plates_bridge, tetrahedron_drop, two_spheres_bridge
+    oracle.build(force=False)
+    cores = oracle.Oracle.max_threads()
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    plan = [("plates_bridge", plates_bridge, {cores: 200, 1: 200}),
+            ("two_spheres_bridge", two_spheres_bridge, {cores: 10, 1: 2}),
+            ("tetrahedron_drop", tetrahedron_drop, {cores: 4, 1: 1})]
+    for name, make, runs in plan:
+        w = make()
+        for threads, steps in runs.items():
+            oracle.Oracle.set_threads(threads)
+            o = oracle.Oracle(w.params, w.bodies, w.rho0, w.phi0)
+            o.step(1)
+            t0 = time.perf_counter()
+            o.step(steps)
+            dt = time.perf_counter() - t0
+            del o
+            rec = {"oracle_timing": name, "shape": list(w.shape), "threads": threads, "steps": steps,
+                   "seconds": round(dt, 3), "MLUPS": round(w.cells * steps / dt / 1e6, 4), "host_cpu": cpu,
+                   "host_threads_available": cores}
+            print(json.dumps(rec), flush=True)
+        oracle.Oracle.set_threads(cores)
+    return 0
 
 
 def batched_sweep(args) -> int:
@@ -236,11 +276,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="two_spheres_bridge")
+    ap.add_argument("--workload", default="tetrahedron_drop")
     ap.add_argument("--n", type=int, default=None, help="grid size override (cubic)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16"])
     ap.add_argument("--lattice", type=int, default=19, choices=[19, 27], help="velocity set (27: Sec. 3.2.1)")
-    ap.add_argument("--tau", type=float, default=None, help="BGK relaxation time (workload default 1.0)")
+    ap.add_argument("--tau", type=float, default=None,
+                    help="BGK relaxation time (workload default: 1.1 for tetrahedron_drop, else 1.0)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16-storage comparison")
@@ -255,7 +296,11 @@ def main() -> int:
     ap.add_argument("--surrogate-steps", type=int, default=1000, help="rigid-body steps (judged every 100)")
     ap.add_argument("--surrogate-refine", type=int, default=100,
                     help="Adam steps on sweep + judged bridges after each judgement (0: none)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only the FP64 CPU oracle: all host cores and one thread on each single-grid workload")
     args = ap.parse_args()
+    if args.oracle_timing:
+        return oracle_timing()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 5)
     if args.batched:

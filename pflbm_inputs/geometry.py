@@ -69,8 +69,31 @@ def plate_phi(shape, core_lo, core_hi, width: float = 4.0):
     return snap(tanh_profile(d - 3.0, width))
 
 
-def sphere_phi(shape, centre, radius, width: float = 4.0):
-    return snap(tanh_profile(sphere_signed_distance(shape, centre, radius), width))
+def _axis_window(n, c, h):
+    """Indices of the cells within h of coordinate c on a periodic axis of n cells (all cells when
+    the window would wrap onto itself)."""
+    lo, hi = int(np.floor(c - h)), int(np.ceil(c + h))
+    if hi - lo + 1 >= n:
+        return np.arange(n)
+    return np.arange(lo, hi + 1) % n
+
+
+def sphere_phi(shape, centre, radius, width: float = 4.0, out=None):
+    """snap(tanh_profile(sphere_signed_distance)), evaluated on the cells within radius + 2 width
+    + 1 of the centre per axis: beyond 2 width outside the surface the profile is below 3.4e-4 and
+    snaps to exactly 0, so the result is the same array as the whole-grid evaluation.  out: a
+    zero-filled array of the grid's shape to write into (returned)."""
+    nz, ny, nx = shape
+    h = radius + 2.0 * width + 1.0
+    ix, iy, iz = (_axis_window(n, c, h) for n, c in ((nx, centre[0]), (ny, centre[1]), (nz, centre[2])))
+    dx = mimg(ix.astype(np.float64) - centre[0], nx) ** 2
+    dy = mimg(iy.astype(np.float64) - centre[1], ny) ** 2
+    dz = mimg(iz.astype(np.float64) - centre[2], nz) ** 2
+    d = np.sqrt((dx[None, None, :] + dy[None, :, None]) + dz[:, None, None]) - radius
+    if out is None:
+        out = np.zeros(shape)
+    out[np.ix_(iz, iy, ix)] = snap(tanh_profile(d, width))
+    return out
 
 
 def liquid_density(d_liquid, rho_l: float, rho_v: float, width: float = 4.0):
@@ -82,11 +105,12 @@ def liquid_density(d_liquid, rho_l: float, rho_v: float, width: float = 4.0):
 _M64 = (1 << 64) - 1
 
 
-def splitmix64_uniform(seed: int, stream: int, n: int, lo: float, hi: float) -> np.ndarray:
+def splitmix64_uniform(seed: int, stream: int, n, lo: float, hi: float) -> np.ndarray:
     """Counter-based uniforms in [lo, hi): SplitMix64 (Steele, Lea, Flood 2014) applied to the
-    counter seed * 2^40 + stream * 2^32 + k, k = 0..n-1; top 53 bits as the mantissa."""
+    counter seed * 2^40 + stream * 2^32 + k, k = 0..n-1 (or k = the entries of n when n is an
+    array of counters); top 53 bits as the mantissa."""
     with np.errstate(over="ignore"):
-        k = np.arange(n, dtype=np.uint64)
+        k = np.asarray(n, dtype=np.uint64) if np.ndim(n) else np.arange(n, dtype=np.uint64)
         base = np.uint64(((seed << 40) + (stream << 32)) & _M64)
         z = (base + k) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(0x9E3779B97F4A7C15)
         z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)

@@ -280,7 +280,9 @@ def tetrahedron_drop(n: int = 256, radius: float = 24.0, gap: float = 4.0, liqui
                      **over) -> Workload:
     """Four spheres at the vertices of a regular tetrahedron with a central liquid drop; liquid
     fraction c = V_L / (V_L + V_S); seeded uniform perturbations on the interface cells of every
-    phase field, then clip and renormalise (Sec. 4.3.2)."""
+    phase field, then clip and renormalise (Sec. 4.3.2).  Runs at the paper's tau = 1.1 (the
+    parameter table of Sec. 3.3) unless tau is given."""
+    over.setdefault("tau", 1.1)
     shape = (n, n, n)
     rv, rl = coexistence_densities()
     c = n / 2.0
@@ -288,13 +290,15 @@ def tetrahedron_drop(n: int = 256, radius: float = 24.0, gap: float = 4.0, liqui
     circ = edge * math.sqrt(6.0) / 4.0
     verts = np.array([(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)], dtype=np.float64) / math.sqrt(3.0) * circ
     centres = [tuple(c + v) for v in verts]
-    phis = np.stack([sphere_phi(shape, ctr, radius, width) for ctr in centres])
+    phis = np.zeros((len(centres),) + shape)
+    for a, ctr in enumerate(centres):
+        sphere_phi(shape, ctr, radius, width, out=phis[a])
     for a in range(phis.shape[0]):
         band = (phis[a] > 0.0) & (phis[a] < 1.0)
         idx = np.flatnonzero(band.reshape(-1))
-        noise = splitmix64_uniform(seed, a, phis[a].size, -amplitude, amplitude)
+        # the uniform of counter k (the cell's flat index) for the band cells only
         flat = phis[a].reshape(-1)
-        flat[idx] += noise[idx]
+        flat[idx] += splitmix64_uniform(seed, a, idx, -amplitude, amplitude)
     phis = np.clip(phis, 0.0, 1.0)
     tot = phis.sum(axis=0)
     over1 = tot > 1.0
@@ -304,9 +308,16 @@ def tetrahedron_drop(n: int = 256, radius: float = 24.0, gap: float = 4.0, liqui
     rr = np.sqrt(mimg(x - c, n) ** 2 + mimg(y - c, n) ** 2 + mimg(z - c, n) ** 2)
     vs = 4 * 4.0 / 3.0 * math.pi * radius ** 3
     target = liquid_fraction / (1.0 - liquid_fraction) * vs
+    # the drop's profile reaches the vapour density exactly (tanh rounds to 1 in FP64) 9.5 widths
+    # outside its surface, so the bisection sums the liquid volume over the cube around the
+    # centre that holds every drop radius it tries
+    win = np.arange(n) if circ + 10.0 * width + 1.0 >= n / 2.0 else \
+        np.arange(int(np.floor(c - circ - 10.0 * width - 1.0)), int(np.ceil(c + circ + 10.0 * width + 1.0)) + 1) % n
+    sub = np.ix_(win, win, win)
+    rr_w, solid_w = rr[sub], solid[sub]
 
     def vol(rd):
-        return _liquid_volume(liquid_density(rr - rd, rl, rv, width), solid, rv, rl)
+        return _liquid_volume(liquid_density(rr_w - rd, rl, rv, width), solid_w, rv, rl)
 
     rd = _bisect(vol, 1.0, circ, target)
     rho = liquid_density(rr - rd, rl, rv, width)
