@@ -22,6 +22,13 @@ SIGMA = 3.3e-2  # profile-integral surface tension at G = -5 (measured by the or
 _print = log
 
 
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
 def _pair(oracle_mod, w, steps, precision, threads=None):
     from paper_1902_10432_amd.simulation import Simulation
     _print(f"case {w.name} shape={w.shape} nb={len(w.bodies)} steps={steps} {precision}")
