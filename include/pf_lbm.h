@@ -142,6 +142,20 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
 int pf_lbm_step(pf_lbm *h, int32_t n_steps);
 
 /*
+ * For callers that cannot allocate device memory around a step (code under stream capture,
+ * serving loops, harnesses that forbid allocation): the same n_steps >= 0 time steps as
+ * pf_lbm_step, bit for bit, with the per-block FP64 force and torque partials of each step taken
+ * from a static array the library holds on every GPU it runs on (192 KiB: at most 256 blocks x
+ * PF_LBM_MAX_BODIES bodies x 6 values), instead of the handle's workspace.  Kernels are launched
+ * one by one on the handle's stream (no HIP graph); the call allocates nothing.  Every call on a
+ * GPU shares that GPU's array and every step rewrites the partials it reads, so calls that run one
+ * after the other are independent, while calls that overlap in time on one GPU (handles on
+ * different streams) race.  Errors: PF_LBM_EINVAL (NULL handle, n_steps < 0, timing enabled),
+ * PF_LBM_EUNSUPPORTED (partials beyond the static size), PF_LBM_EDEVICE.
+ */
+int pf_lbm_step_noalloc(pf_lbm *h, int32_t n_steps);
+
+/*
  * Synchronise the stream and copy the body state to HOST arrays of n_bodies x 3 doubles each
  * (any pointer may be NULL): F, T = total force and torque of the last step (momentum exchange
  * + pseudopotential reaction + repulsion, torques about the centres); X = centre of mass;

@@ -39,7 +39,7 @@ PF_LBM_FIELD_PHI = 16
 PF_LBM_DST_F64 = 0
 PF_LBM_DST_F32 = 1
 
-EXPORTED = ("pf_lbm_init", "pf_lbm_step", "pf_lbm_forces", "pf_lbm_fields", "pf_lbm_diagnostics",
+EXPORTED = ("pf_lbm_init", "pf_lbm_step", "pf_lbm_step_noalloc", "pf_lbm_forces", "pf_lbm_fields", "pf_lbm_diagnostics",
             "pf_lbm_timing", "pf_lbm_force_history", "pf_lbm_step_batch", "pf_lbm_autotune", "pf_lbm_destroy",
             "pf_lbm_last_error")
 
@@ -90,6 +90,8 @@ def load_library():
                                 C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)]
     lib.pf_lbm_step.restype = C.c_int
     lib.pf_lbm_step.argtypes = [C.c_void_p, C.c_int32]
+    lib.pf_lbm_step_noalloc.restype = C.c_int
+    lib.pf_lbm_step_noalloc.argtypes = [C.c_void_p, C.c_int32]
     lib.pf_lbm_forces.restype = C.c_int
     lib.pf_lbm_forces.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
     lib.pf_lbm_fields.restype = C.c_int
@@ -132,6 +134,10 @@ def pf_lbm_init(cfg: PfLbmConfig, n_bodies: int, bodies, rho0: np.ndarray, phi0,
 
 def pf_lbm_step(h, n_steps: int) -> int:
     return load_library().pf_lbm_step(h, int(n_steps))
+
+
+def pf_lbm_step_noalloc(h, n_steps: int) -> int:
+    return load_library().pf_lbm_step_noalloc(h, int(n_steps))
 
 
 def pf_lbm_forces(h, n_bodies: int):

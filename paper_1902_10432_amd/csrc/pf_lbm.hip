@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -28,12 +29,23 @@ constexpr uint32_t EV_CAP = 1u << 16;
 // steps of per-body force / torque history kept on the device (ring)
 constexpr int HIST_CAP = 8192;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+// largest grid of the force scan (per-block partials of every body)
+constexpr int FORCE_GRID_MAX = 256;
+// per-block FP64 force / torque partials of one step: FORCE_GRID_MAX blocks x PF_LBM_MAX_BODIES
+// bodies x 6 components (192 KiB)
+constexpr size_t STATIC_PARTS = (size_t)FORCE_GRID_MAX * PF_LBM_MAX_BODIES * 6;
+constexpr int MAX_DEVICES = 64;
 
 struct Layout {
     size_t fA, fB, psi, psiB, phiA, phiB, mask, nbw, bodies, state, sigma, pforce, cpart, evlist, hist, total;
 };
 
 }  // namespace
+
+// Force partials of pf_lbm_step_noalloc: one copy per GPU (each device holds its own instance of
+// the array), shared by every such call on that GPU.  Host code never uses this name as an
+// address: the device address comes from hipGetSymbolAddress (static_parts below).
+static __device__ __align__(256) double scratch[STATIC_PARTS];
 
 struct pf_lbm {
     pf_lbm_config cfg;
@@ -302,7 +314,7 @@ void launch_advect(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const Bod
 
 // one time step (Sec. 3): fluid, body forces + rigid update, phase fields, reclassification
 template <typename S, class Lat>
-int enqueue_step(pf_lbm *h) {
+int enqueue_step(pf_lbm *h, double *parts = nullptr) {
     using T = ArT<S>;
     const Prm<T> p = make_prm<T>(h);
     const int par = (int)(h->steps & 1);
@@ -317,7 +329,8 @@ int enqueue_step(pf_lbm *h) {
     BodyDev *cur = btab + par * nbm, *next = btab + (par ^ 1) * nbm;
     StepState *st = (StepState *)(h->ws + h->L.state);
     const double *sigma = (const double *)(h->ws + h->L.sigma);
-    double *pforce = (double *)(h->ws + h->L.pforce);
+    // per-block force partials: the workspace's, or the caller-supplied static copy
+    double *pforce = parts ? parts : (double *)(h->ws + h->L.pforce);
     ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
     const dim3 gd((unsigned)((h->N + h->psi_bs - 1) / h->psi_bs)), b(256);
     hipStream_t s = h->stream;
@@ -505,7 +518,7 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     // 1024, the launch and drain of more blocks costing more than their extra parallelism gains;
     // on the 256^3 four-sphere workload 1024 beat 512 by 2 %)
     const int box_grid = std::min(box_blocks, vol0 > (1LL << 20) ? 1024 : 512);
-    const int force_grid = std::min((box_blocks + 3) / 4, 256);
+    const int force_grid = std::min((box_blocks + 3) / 4, FORCE_GRID_MAX);
     const int cgrid = box_grid;
     const Layout L = make_layout(Np, n_bodies, cfg->precision, cfg->lattice, std::max(cgrid, box_grid), force_grid);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
@@ -592,14 +605,33 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
 
 namespace {
 
-int eager_step(pf_lbm *h) {
+int eager_step(pf_lbm *h, double *parts = nullptr) {
     if (h->q == 27)
-        return h->prec == PF_LBM_FP64 ? enqueue_step<double, D3Q27>(h)
-               : h->prec == PF_LBM_FP32 ? enqueue_step<float, D3Q27>(h)
-                                        : enqueue_step<half_t, D3Q27>(h);
-    return h->prec == PF_LBM_FP64 ? enqueue_step<double, D3Q19>(h)
-           : h->prec == PF_LBM_FP32 ? enqueue_step<float, D3Q19>(h)
-                                    : enqueue_step<half_t, D3Q19>(h);
+        return h->prec == PF_LBM_FP64 ? enqueue_step<double, D3Q27>(h, parts)
+               : h->prec == PF_LBM_FP32 ? enqueue_step<float, D3Q27>(h, parts)
+                                        : enqueue_step<half_t, D3Q27>(h, parts);
+    return h->prec == PF_LBM_FP64 ? enqueue_step<double, D3Q19>(h, parts)
+           : h->prec == PF_LBM_FP32 ? enqueue_step<float, D3Q19>(h, parts)
+                                    : enqueue_step<half_t, D3Q19>(h, parts);
+}
+
+// Device address of this GPU's copy of the static force partials, looked up once per device
+// (with that device current) and kept.
+std::mutex g_static_mu;
+double *g_static_ptr[MAX_DEVICES] = {};
+
+int static_parts(pf_lbm *h, double **out) {
+    int dev = -1;
+    HIPCHK(h, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(h, PF_LBM_EUNSUPPORTED, "device %d beyond %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(h, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_static_ptr[dev] = (double *)ptr;
+    }
+    *out = g_static_ptr[dev];
+    return PF_LBM_OK;
 }
 
 constexpr int GRAPH_STEPS[2] = {2, 32};
@@ -665,6 +697,25 @@ int pf_lbm_step(pf_lbm *h, int32_t n_steps) {
     }
     for (; n > 0; --n) {
         const int rc = eager_step(h);
+        if (rc != PF_LBM_OK) return rc;
+    }
+    return PF_LBM_OK;
+}
+
+int pf_lbm_step_noalloc(pf_lbm *h, int32_t n_steps) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    if (n_steps < 0) return fail(h, PF_LBM_EINVAL, "n_steps must be >= 0");
+    if (h->timing) return fail(h, PF_LBM_EINVAL, "pf_lbm_step_noalloc does not record timing events");
+    const size_t need = (size_t)h->force_grid * std::max(h->nb, 1) * 6;
+    if (need > STATIC_PARTS)
+        return fail(h, PF_LBM_EUNSUPPORTED, "force partials of %zu doubles exceed the static %zu", need, STATIC_PARTS);
+    double *parts = nullptr;
+    const int rc0 = static_parts(h, &parts);
+    if (rc0 != PF_LBM_OK) return rc0;
+    // kernels launched one by one (no graph is captured or replayed): every step writes all the
+    // partials it reads, so the array needs no clearing
+    for (int k = 0; k < n_steps; ++k) {
+        const int rc = eager_step(h, parts);
         if (rc != PF_LBM_OK) return rc;
     }
     return PF_LBM_OK;
