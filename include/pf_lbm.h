@@ -195,12 +195,18 @@ int pf_lbm_force_history(pf_lbm *h, int32_t max_steps, double *out, int32_t *n_o
  * Returns the first error (its message on that handle). */
 int pf_lbm_step_batch(pf_lbm *const *handles, int32_t n, int32_t n_steps);
 
-/* Autotuner of the launch shapes that leave the arithmetic unchanged: the rows of the collide
- * block (64 x 1, 2 or 4 threads) and the block size of the pseudopotential kernel (128 or 256).
- * Each candidate runs 1 + steps_per_candidate steps of the simulation itself (the state
- * advances), timed with HIP events; the fastest is kept.  out3 (HOST, may be NULL): chosen rows,
- * chosen block size, its mean step time in ms. */
+/* Autotuner of the tile shape of the fluid pass, which leaves the arithmetic unchanged: tiles of
+ * 64 x 4 or 64 x 8 nodes (FP64 populations: 64 x 4) marching z-chunks of 4, 8, 16, 32 or 64
+ * planes.  Each candidate runs 1 + steps_per_candidate steps of the simulation itself (the state
+ * advances), timed with HIP events; the fastest is kept.  out3 (HOST, may be NULL): chosen tile
+ * rows, chosen planes per chunk, its mean step time in ms. */
 int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3);
+
+/* Tile shape of the fluid pass (as pf_lbm_autotune chooses it, or a shape kept from an earlier
+ * tuning): tiles of 64 x rows nodes (rows 4 or 8; 4 with FP64 populations) marching z-chunks of
+ * planes >= 1 planes.  The arithmetic does not depend on it.  Errors: PF_LBM_EUNSUPPORTED (rows
+ * not built for the precision and lattice), PF_LBM_EINVAL. */
+int pf_lbm_set_tile(pf_lbm *h, int32_t rows, int32_t planes);
 
 /* Release the handle (the workspace stays the caller's).  NULL is ignored. */
 void pf_lbm_destroy(pf_lbm *h);

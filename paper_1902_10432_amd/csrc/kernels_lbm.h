@@ -1,6 +1,6 @@
-// Fluid kernels of the step: fused force + Guo-BGK collision + push streaming with moving-wall
-// bounce-back, and the per-body force/torque sums (the pseudopotential pass, which also closes
-// the previous step's node conversions, is in kernels_pf.h).
+// Fluid kernels of the step: the fluid pass (density and pseudopotential, force, Guo-BGK
+// collision, push streaming with moving-wall bounce-back, in one read of the populations) and
+// the per-body force/torque sums.
 #pragma once
 
 #include "device_common.h"
@@ -74,73 +74,55 @@ __device__ __forceinline__ void wall_velocity(const Prm<T> &p, const BodyDev &B,
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// 3-D launch (64 x R threads per block, R = 1, 2 or 4, grid ceil(nx/64) x ceil(ny/R) x nz) with the
-// flat block id remapped so that each XCD works on a contiguous range of planes.
-__device__ __forceinline__ bool cell_of_block(int nx, int ny, int &x, int &y, int &z) {
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const int r = xcd_block(lin, gx * gy * gridDim.z);
-    const int bz = r / (gx * gy), rem = r - bz * gx * gy, by = rem / gx, bxx = rem - by * gx;
-    x = bxx * 64 + (int)threadIdx.x;
-    y = by * (int)blockDim.y + (int)threadIdx.y;
-    z = bz;
-    return x < nx && y < ny;
-}
-
-// One fluid node per thread: load its 19 post-stream populations, form the Shan-Chen/Benzi force
-// from the 18 neighbour pseudopotentials (solid neighbours act with their wetting density),
-// collide with BGK + Guo forcing at the half-force velocity, and push each post-collision
-// population to its neighbour, or reflect it half-way into the node's own opposite slot with the
-// moving-wall term when the neighbour is solid.  The wall terms are taken back from the rest
-// population (Sec. 3.2.1, 3.2.2, 3.2.3).  Solid nodes are skipped and receive nothing.
+// ---- the fluid pass: density, pseudopotential, force, collision and push streaming -----------
 //
-// With bodies, the first block also publishes the step's box, solid radii, volume terms and event
-// flag from the previous reclassification (publish_step_state) before its own cells: that short
-// reduction chain then hides behind the longest pass of the step instead of costing a launch.
+// One pass over the populations per step.  A block owns a tile of 64 x TY nodes in the x-y plane
+// and marches a chunk of tz planes along z.  The Shan-Chen/Benzi force at a node needs the
+// pseudopotential of its 18 (26) neighbours at the same time level, so the block keeps a window
+// of three planes of psi for its tile and a one-node halo in LDS: before colliding plane z it
+// forms rho and psi of plane z + 1 from the post-stream populations (the tile's own nodes and
+// the halo), so every population is read from HBM once.  The tile's own populations of plane
+// z + 1 wait in LDS (each thread in its own slots) until plane z + 1 is collided; halo nodes
+// and the two planes before and after the chunk cost a density-only read (mostly served by L2,
+// where the neighbouring tiles read the same lines).  The pseudopotential of every node is
+// written once, for the force scan and read-out.
+
+// Collision and streaming of one fluid node (Sec. 3.2.1, 3.2.2, 3.2.3): sv holds its stored
+// post-stream populations, psin(I) the pseudopotential of its neighbour in direction I, psi0 its
+// own.  Forms the force from the neighbours' psi (solid neighbours act with their wetting
+// density), collides with BGK + Guo forcing at the half-force velocity, and pushes each
+// post-collision population to its neighbour, or, when the neighbour is solid (bit i of
+// solid_dirs), reflects it half-way into the node's own opposite slot (with the moving-wall term
+// where wall_in_fluid_pass).  rin: reference density of the node's stored inputs (FP16 storage).
 //
 // Arithmetic is organised by opposite pairs (c_opp = -c): with cu = c.v, cF = c.F,
 //   f*_i = (1 - 1/tau) f_i + w (even + odd),  f*_opp = (1 - 1/tau) f_opp + w (even - odd),
 //   even = rho/tau (1 - 3/2 v.v) - 3 g v.F + 9/2 rho/tau cu^2 + 9 g cu cF,  odd = 3 rho/tau cu + 3 g cF,
 // g = 1 - 1/(2 tau), which is the BGK relaxation to the second-order equilibrium plus the Guo term.
-template <typename S, class L>
-__global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *__restrict__ fin, S *__restrict__ fout,
-                                                        const ArT<S> *__restrict__ psi,
-                                                        const ArT<S> *__restrict__ psi_prev,
-                                                        const cell_t *__restrict__ mask,
-                                                        BodyDev *bodies, int parity, StepState *st,
-                                                        const ClassifyPart *__restrict__ cpart, int cblk,
-                                                        const uint32_t *__restrict__ nbw) {
+// Where the moving-wall term of the bounce-back is added (Sec. 3.2.2).  FP32 and FP64: by the force
+// scan, which visits exactly the nodes next to solids, so the fluid pass needs no body data and
+// stays lean.  FP16 storage: in the fluid pass, so that the reflected population f*_i + g_i is
+// rounded to FP16 once (adding g to an already rounded f*_i and rounding again was measured to
+// triple the body-force error of the form).
+template <typename S>
+constexpr bool wall_in_fluid_pass() {
+    return sizeof(S) == 2;
+}
+
+template <typename S, class L, typename PsiN>
+__device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, ArT<S> rin, PsiN psin, ArT<S> psi0,
+                                             S *__restrict__ fout, uint32_t solid_dirs, int x, int y, int z,
+                                             long long Np, const cell_t *__restrict__ mask,
+                                             const BodyDev *__restrict__ bodies) {
     using T = ArT<S>;
-    if (cpart && (blockIdx.x | blockIdx.y | blockIdx.z) == 0)
-        publish_step_state((int)threadIdx.y, (int)blockDim.y, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart,
-                           cblk);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    int x, y, z;
-    if (!cell_of_block(nx, ny, x, y, z)) return;
     const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
-    const cell_t w0 = mask[idx];
-    if (w0 & C_SOLID) return;
-    // bit i: the neighbour in direction i is solid (D3Q19: kept in the cell word; D3Q27: the
-    // neighbour-bit word of the node)
-    uint32_t solid_dirs;
-    if constexpr (L::kBits)
-        solid_dirs = w0 & C_NBMASK;
-    else
-        solid_dirs = nbw[idx];
-    const uint32_t ib = idx * (uint32_t)sizeof(T);      // psi (arithmetic type)
-    const uint32_t is = idx * (uint32_t)sizeof(S);      // populations (storage type)
-    const NbrU nb(x, y, z, nx, ny, nz, (int)sizeof(T));
+    const uint32_t is = idx * (uint32_t)sizeof(S);  // populations (storage type)
     const NbrU ns(x, y, z, nx, ny, nz, (int)sizeof(S));
-    const long long Np = p.Np;
     constexpr bool H = sizeof(S) == 2;  // FP16 storage: deviations from w_i R
 
     T f[L::Q];
-    {
-        const T rin = H ? ref_density(psi_prev[idx], p.rho0) : T(0);  // reference of the inputs
-        sfor<L::Q>([&](auto I) {
-            f[I] = pop_get<S>(ldb_nt(fin + (long long)I * Np, is), Dir<decltype(I)::value, L>::template w<T>() * rin);
-        });
-    }
+    sfor<L::Q>([&](auto I) { f[I] = pop_get<S>(sv[I], Dir<decltype(I)::value, L>::template w<T>() * rin); });
     // moments from pair sums and differences
     T rho = f[0], jx = T(0), jy = T(0), jz = T(0);
     sfor<(L::Q - 1) / 2>([&](auto K) {
@@ -160,7 +142,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     T rdst[L::Q];  // FP16 form: reference density of each push destination
     sfor<(L::Q - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;
-        const T pa = ldb(psi, nb.template at<i>(ib)), pb = ldb(psi, nb.template at<i + 1>(ib));
+        const T pa = psin(std::integral_constant<int, i>{}), pb = psin(std::integral_constant<int, i + 1>{});
         if constexpr (H) {
             rdst[i] = ref_density(pa, p.rho0);
             rdst[i + 1] = ref_density(pb, p.rho0);
@@ -180,7 +162,6 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
             s3z += T(Dir<i, L>::z) * dp;
         }
     });
-    const T psi0 = ldb(psi, ib);
     const T gp = -p.G * psi0;
     const T rown = H ? ref_density(psi0, p.rho0) : T(0);  // reference of this node's own slots
     const T w1 = T(L::wshell[1]), w2 = T(L::wshell[2]);
@@ -218,75 +199,36 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
         f[i + 1] = keep * f[i + 1] + w * (even - odd);
     });
 
-    // streaming
+    // streaming: push to the neighbour, or reflect half-way into the node's own opposite slot
+    // when the neighbour is solid
+    T drho = T(0);
     if (!solid_dirs) {
         sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0)
                 stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
         });
-        stb(fout, is, pop_put<S>(f[0], Dir<0, L>::template w<T>() * rown));
-        return;
-    }
-    const NbrU ne(x, y, z, nx, ny, nz, 1);
-    T drho = T(0);
-    if constexpr (L::kBits && sizeof(S) != 2) {
-        // D3Q19, FP32 and FP64 populations: the owners of the solid neighbours come from one
-        // round of gathers, then the reflections run body by body (wave-uniform loop) with the
-        // body read once.  c_i . u_w at the link midpoint x + c_i/2 equals c_i . u_w(x), as
-        // c_i . (omega x c_i) = 0, so the node's rigid velocity serves every link.  (Loads inside
-        // per-link branches wait for memory once per link; this path keeps the interface waves
-        // from trailing the pass.  The FP16-storage form keeps the per-link path: its encoded
-        // reflections are sensitive to the rounding of the wall term.)
-        uint32_t own[(L::Q + 7) / 8] = {};
-        uint32_t touched = 0;
+    } else if constexpr (!wall_in_fluid_pass<S>()) {
+        // f*_i into slot opp(i); the force scan adds the moving-wall term and the mass correction
         sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0) {
-                const cell_t mw = ldb(mask, ne.template at<i>(idx) * 4u);
-                if (!(solid_dirs & (1u << i))) {
-                    stb(fout + (long long)i * Np, ns.template at<i>(is),
-                        pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
-                } else {
-                    const uint32_t o = (uint32_t)owner_of(mw);
-                    own[i >> 3] |= o << (4 * (i & 7));
-                    touched |= 1u << o;
-                }
+                if (!(solid_dirs & (1u << i)))
+                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
+                else
+                    stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i], Dir<i, L>::template w<T>() * rown));
             }
         });
-        for (int b = 0; b < p.nb; ++b) {
-            if (!__ballot((touched >> b) & 1u)) continue;
-            if (!((touched >> b) & 1u)) continue;
-            const BodyDev &Bd = bodies[b];
-            const double rx = mimg_r(x - Bd.X[0], nx, p.inv_n[0]), ry = mimg_r(y - Bd.X[1], ny, p.inv_n[1]),
-                         rz = mimg_r(z - Bd.X[2], nz, p.inv_n[2]);
-            const double u0x = Bd.V[0] + (Bd.W[1] * rz - Bd.W[2] * ry), u0y = Bd.V[1] + (Bd.W[2] * rx - Bd.W[0] * rz),
-                         u0z = Bd.V[2] + (Bd.W[0] * ry - Bd.W[1] * rx);
-            sfor<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                if constexpr (i > 0) {
-                    if ((solid_dirs & (1u << i)) && ((own[i >> 3] >> (4 * (i & 7))) & 15u) == (uint32_t)b) {
-                        double cuw = 0.0;
-                        if constexpr (Dir<i, L>::x != 0) cuw += Dir<i, L>::x * u0x;
-                        if constexpr (Dir<i, L>::y != 0) cuw += Dir<i, L>::y * u0y;
-                        if constexpr (Dir<i, L>::z != 0) cuw += Dir<i, L>::z * u0z;
-                        const T gw = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
-                        stb(fout + (long long)Dir<i, L>::opp * Np, is,
-                            pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
-                        drho += gw;
-                    }
-                }
-            });
-        }
     } else {
+        // f*_i + g_i into slot opp(i), g_i = -2 rho w_i (c_i . u_w) / c_s^2 with u_w the rigid
+        // velocity at the link midpoint x + c_i / 2; the rest population gives back the g_i
+        const NbrU ne(x, y, z, nx, ny, nz, 1);
         sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0) {
                 if (!(solid_dirs & (1u << i))) {
                     stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
                 } else {
-                    // reflected into direction opp(i) with g = -2 rho w_i (c_i . u_w) / c_s^2, u_w at
-                    // the link midpoint x + c_i / 2
                     const BodyDev &Bd = bodies[owner_of(mask[ne.template at<i>(idx)])];
                     double uwx, uwy, uwz;
                     wall_velocity(p, Bd, x + 0.5 * Dir<i, L>::x, y + 0.5 * Dir<i, L>::y, z + 0.5 * Dir<i, L>::z, uwx, uwy, uwz);
@@ -301,11 +243,275 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
     stb(fout, is, pop_put<S>(f[0] - drho, Dir<0, L>::template w<T>() * rown));
 }
 
+// LDS of the fluid pass: the psi window (3 planes of the tile and its halo, 66 x (TY + 2)), the
+// tile's populations of the plane being collided ([direction][node of the tile], stored form),
+// and, where the budget allows (DMA), the halo's populations, cell words and previous psi of
+// two planes, loaded straight into LDS.
+template <typename S, class L, int TY, bool DMA>
+struct FluidLds {
+    // halo entries: the rows below and above the tile (64 each), the two columns (TY + 2 each)
+    static constexpr int NH = DMA ? 128 + 2 * (TY + 2) : 1, NB = DMA ? 2 : 1;
+    ArT<S> ring[3][TY + 2][66];
+    S pop[L::Q][64 * TY];
+    S hpop[NB][L::Q][NH];
+    cell_t hmask[NB][NH];
+};
+// a block is four waves; each thread owns RPT rows of the tile (TY = 4 RPT)
+constexpr int FLUID_WAVES = 4;
+template <typename S, class L, int RPT>
+constexpr bool fluid_tile_fits() {
+    return sizeof(FluidLds<S, L, FLUID_WAVES * RPT, false>) <= 65536;
+}
+// direct loads into LDS move one dword per lane (a shorter element would still take a dword slot
+// of LDS per lane): FP32 populations only
+template <typename S, class L, int RPT>
+constexpr bool fluid_halo_dma() {
+    return sizeof(S) == 4 && sizeof(FluidLds<S, L, FLUID_WAVES * RPT, true>) <= 65536;
+}
+
+// one node's inputs of one plane: its stored populations, cell word and (FP16) previous psi
+template <typename S, class L>
+struct NodeIn {
+    S v[L::Q];
+    cell_t m;
+    ArT<S> pp;
+};
+
+// psi of a node from its inputs (Sec. 3.2.3): fluid 1 - exp(-rho/rho0) with rho the sum of the
+// populations (FP16: rho = R + sum of the stored deviations, the weights summing to one); a
+// solid node carries the value of its body's wetting density.  v(I): stored population I.
+template <typename S, class L, typename V>
+__device__ __forceinline__ ArT<S> node_psi_of(const Prm<ArT<S>> &p, const BodyDev *__restrict__ bodies, cell_t m,
+                                              ArT<S> pp, V v) {
+    using T = ArT<S>;
+    if (m & C_SOLID) return (T)bodies[owner_of(m)].psi_s;
+    T r = T(0);
+    if constexpr (sizeof(S) == 2) r = ref_density(pp, p.rho0);
+    sfor<L::Q>([&](auto I) { r += (T)v(I); });
+    return -expm1(-r * p.inv_rho0);
+}
+
+// The fluid pass (see above).  Launch: 256 threads per block (four waves, one x-row of 64 nodes
+// per wave and row set), tiles of 64 x TY nodes with TY = 4 RPT (thread (tx, w) owns rows w,
+// w + 4, ..), a 1-D grid of ceil(nx/64) * ceil(ny/TY) * ceil(nz/tz) blocks; blocks are ordered so
+// that each XCD holds a contiguous run of tiles (a z-chunk of neighbouring tiles shares an L2).
+//
+// Software pipeline along z: while plane z is collided, the tile's own populations of plane z + 2
+// are in flight into registers and (DMA) the halo's straight into LDS; at the top of the next
+// pass they have landed, psi of plane z + 2 is formed, and so on.  Instantiations whose halo
+// buffers do not fit the LDS budget load the halo of each plane just before its psi is formed.
+//
+// With bodies, the first block also publishes the step's box, solid radii, volume terms and event
+// flag from the previous reclassification (publish_step_state) before its own cells: that short
+// reduction chain then hides behind the longest pass of the step instead of costing a launch.
+template <typename S, class L, int RPT>
+__global__ __launch_bounds__(64 * FLUID_WAVES) void k_collide_stream(Prm<ArT<S>> p, const S *__restrict__ fin,
+                                                                     S *__restrict__ fout, ArT<S> *__restrict__ psi,
+                                                                     const ArT<S> *__restrict__ psi_prev,
+                                                                     const cell_t *__restrict__ mask, BodyDev *bodies,
+                                                                     int parity, StepState *st,
+                                                                     const ClassifyPart *__restrict__ cpart, int cblk,
+                                                                     const uint32_t *__restrict__ nbw, int tz) {
+    using T = ArT<S>;
+    constexpr int W = FLUID_WAVES, TY = W * RPT;
+    constexpr bool DMA = fluid_halo_dma<S, L, RPT>();
+    static_assert(fluid_tile_fits<S, L, RPT>(), "LDS of the fluid pass above 64 KB");
+    __shared__ FluidLds<S, L, TY, DMA> lds;
+    constexpr bool H = sizeof(S) == 2;
+    const int tid = (int)threadIdx.x, tx = tid & 63, wv = tid >> 6;
+    if (cpart && blockIdx.x == 0)
+        publish_step_state(wv, W, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart, cblk);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int tiles_x = (nx + 63) / 64, tiles_y = (ny + TY - 1) / TY, tiles = tiles_x * tiles_y;
+    const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int chunk = b / tiles, tile = b - chunk * tiles;
+    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    const int x0 = txi * 64, y0 = tyi * TY, zs = chunk * tz, ze = min(zs + tz, nz);
+    const int x = x0 + tx;
+    const uint32_t pl = (uint32_t)nx * (uint32_t)ny;
+    // rows of this thread: ty = wv + W r; the node whose psi its window entry holds (a partial
+    // tile's entries past the grid edge hold the periodic images the last nodes need)
+    bool valid[RPT];
+    uint32_t own_xy[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int y = y0 + wv + W * r;
+        valid[r] = x < nx && y < ny;
+        own_xy[r] = (uint32_t)wrapi(x, nx) + (uint32_t)nx * (uint32_t)wrapi(y, ny);
+    }
+    // halo entry of this thread: row ly = -1 (wave 0), row ly = TY (wave 1), the two columns
+    // lx = -1 and 64 for ly = -1..TY (wave 3, lanes 0 .. 2 TY + 3); hs: the wave's 64 entries
+    // in the halo buffers
+    int hlx = 0, hly = 0, hs = 0;
+    bool halo = false;
+    if (wv == 0 || wv == 1) {
+        halo = true;
+        hlx = tx;
+        hly = wv == 0 ? -1 : TY;
+        hs = 64 * wv;
+    } else if (wv == 3) {
+        halo = tx < 2 * (TY + 2);
+        hlx = (tx & 1) ? 64 : -1;
+        hly = (tx >> 1) - 1;
+        hs = 128;
+    }
+    const uint32_t halo_xy = (uint32_t)wrapi(x0 + hlx, nx) + (uint32_t)nx * (uint32_t)wrapi(y0 + hly, ny);
+    auto slot = [&](int zz) { return (zz - zs + 1) % 3; };
+    auto hbuf = [&](int zz) { return DMA ? ((zz - zs + 1) & 1) : 0; };
+    // The plane stride is re-read (opaque to the compiler) in every pass of the loop, so the 2 Q
+    // plane addresses are formed on the scalar unit where they are used instead of being hoisted
+    // out of the loop, where they would occupy more scalar registers than there are.
+    auto plane_stride = [&]() {
+        long long np = p.Np;
+        asm volatile("" : "+s"(np));
+        return np;
+    };
+    // loads of the own nodes' inputs of plane zz (issued, not waited for)
+    auto load_own = [&](int zz, NodeIn<S, L> (&o)[RPT]) {
+        const uint32_t zo = pl * (uint32_t)wrapi(zz, nz);
+        const long long np = plane_stride();
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const uint32_t idx = own_xy[r] + zo;
+            o[r].m = mask[idx];
+            o[r].pp = H ? psi_prev[idx] : T(0);
+            const uint32_t is = idx * (uint32_t)sizeof(S);
+            sfor<L::Q>([&](auto I) { o[r].v[I] = ldb(fin + (long long)I * np, is); });
+        }
+    };
+    // the halo's inputs of plane zz straight into LDS buffer hb (DMA)
+    auto halo_issue = [&](int zz, int hb) {
+        if constexpr (DMA) {
+            if (!halo) return;
+            const uint32_t hidx = halo_xy + pl * (uint32_t)wrapi(zz, nz);
+            const long long np = plane_stride();
+            sfor<L::Q>([&](auto I) {
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(fin + (long long)I * np + hidx),
+                    (__attribute__((address_space(3))) void *)&lds.hpop[hb][I][hs], 4, 0, 0);
+            });
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(mask + hidx),
+                                             (__attribute__((address_space(3))) void *)&lds.hmask[hb][hs], 4, 0, 0);
+        }
+    };
+    // psi of the halo entry of plane zz into the window: from the LDS buffer (DMA) or loaded now
+    auto halo_psi = [&](int zz) {
+        if (!halo) return;
+        T hp;
+        if constexpr (DMA) {
+            const int hb = hbuf(zz), k = hs + tx;
+            hp = node_psi_of<S, L>(p, bodies, lds.hmask[hb][k], T(0),
+                                   [&](auto I) { return lds.hpop[hb][decltype(I)::value][k]; });
+        } else {
+            NodeIn<S, L> hi;
+            const uint32_t hidx = halo_xy + pl * (uint32_t)wrapi(zz, nz);
+            const long long np = plane_stride();
+            hi.m = mask[hidx];
+            hi.pp = H ? psi_prev[hidx] : T(0);
+            const uint32_t is = hidx * (uint32_t)sizeof(S);
+            sfor<L::Q>([&](auto I) { hi.v[I] = ldb(fin + (long long)I * np, is); });
+            hp = node_psi_of<S, L>(p, bodies, hi.m, hi.pp, [&](auto I) { return hi.v[decltype(I)::value]; });
+        }
+        lds.ring[slot(zz)][hly + 1][hlx + 1] = hp;
+    };
+    auto own_psi = [&](int zz, const NodeIn<S, L> (&o)[RPT]) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            lds.ring[slot(zz)][wv + W * r + 1][tx + 1] =
+                node_psi_of<S, L>(p, bodies, o[r].m, o[r].pp, [&](auto I) { return o[r].v[decltype(I)::value]; });
+    };
+
+    NodeIn<S, L> A[RPT], B[RPT];
+    // prologue: psi of planes zs - 1 and zs, populations of plane zs into LDS, plane zs + 1 in
+    // flight
+    load_own(zs - 1, A);
+    own_psi(zs - 1, A);
+    halo_issue(zs - 1, hbuf(zs - 1));
+    halo_issue(zs, hbuf(zs));
+    load_own(zs, A);
+    load_own(zs + 1, B);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    halo_psi(zs - 1);
+    halo_psi(zs);
+    own_psi(zs, A);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) sfor<L::Q>([&](auto I) { lds.pop[I][tid + 64 * W * r] = A[r].v[I]; });
+    cell_t cm[RPT];  // cell words of the plane being collided
+    T cpp[RPT];      // and their previous psi (FP16)
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        cm[r] = A[r].m;
+        cpp[r] = A[r].pp;
+    }
+    halo_issue(zs + 1, hbuf(zs + 1));
+    for (int z = zs; z < ze; ++z) {
+        // plane z + 1 has landed (own populations in B, halo in its LDS buffer); every wave is done
+        // with the previous plane's window entries and halo buffer
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        own_psi(z + 1, B);
+        halo_psi(z + 1);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) A[r] = B[r];
+        if (z + 2 <= ze) {
+            load_own(z + 2, B);
+            halo_issue(z + 2, hbuf(z + 2));
+        }
+        __syncthreads();
+        const uint32_t zo = pl * (uint32_t)z;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int ty = wv + W * r;
+            // own populations of plane z from LDS, those of plane z + 1 in their place
+            S cur[L::Q];
+            sfor<L::Q>([&](auto I) { cur[I] = lds.pop[I][tid + 64 * W * r]; });
+            sfor<L::Q>([&](auto I) { lds.pop[I][tid + 64 * W * r] = A[r].v[I]; });
+            // the stores stay here, ahead of the collision (sunk below it, they would keep the next
+            // plane's populations in registers through the collision)
+            asm volatile("" ::: "memory");
+            if (valid[r]) {
+                const uint32_t idx = own_xy[r] + zo;
+                // the node's entry in each window plane: neighbours are fixed offsets from it
+                const T *rm = &lds.ring[slot(z - 1)][ty + 1][tx + 1], *r0 = &lds.ring[slot(z)][ty + 1][tx + 1],
+                        *rp = &lds.ring[slot(z + 1)][ty + 1][tx + 1];
+                const T psi0 = *r0;
+                psi[idx] = psi0;
+                const cell_t w0 = cm[r];
+                if (!(w0 & C_SOLID)) {
+                    // bit i: the neighbour in direction i is solid (D3Q19: kept in the cell word;
+                    // D3Q27: the neighbour-bit word of the node)
+                    uint32_t solid_dirs;
+                    if constexpr (L::kBits)
+                        solid_dirs = w0 & C_NBMASK;
+                    else
+                        solid_dirs = nbw[idx];
+                    const T rin = H ? ref_density(cpp[r], p.rho0) : T(0);  // reference of the inputs
+                    collide_push<S, L>(
+                        p, cur, rin,
+                        [&](auto I) {
+                            constexpr int i = decltype(I)::value;
+                            constexpr int o = Dir<i, L>::y * 66 + Dir<i, L>::x;
+                            return Dir<i, L>::z < 0 ? rm[o] : (Dir<i, L>::z > 0 ? rp[o] : r0[o]);
+                        },
+                        psi0, fout, solid_dirs, x, y0 + ty, z, plane_stride(), mask, bodies);
+                }
+            }
+            cm[r] = A[r].m;
+            cpp[r] = A[r].pp;
+        }
+    }
+}
+
 // Per-body force and torque sums of the step, one box node per thread (Sec. 3.1.1, 3.1.2, 3.2.2):
-//  * fluid nodes next to solid nodes: momentum exchange c_i (2 f*_i + g) for each link into body
-//    b, recovered from the reflected population f_opp(i) = f*_i + g written by k_collide_stream,
-//    plus the pseudopotential reaction +G psi(x) w_i psi(varrho_b) c_i (opposite of the fluid's
-//    share), with the link midpoint as lever arm;
+//  * fluid nodes next to solid nodes: the fluid pass reflected each population f*_i heading into
+//    a solid node into the node's opposite slot; unless the fluid pass did so (wall_in_fluid_pass),
+//    this kernel completes the moving-wall bounce-back of Sec. 3.2.2 there -- the slot becomes
+//    f*_i + g_i with g_i = -2 rho w_i (c_i . u_w) / c_s^2 and the rest population gives back the
+//    sum of the g_i (mass correction) -- and it adds to body b the momentum exchange
+//    c_i (2 f*_i + g_i) of each link into b, plus the pseudopotential reaction
+//    +G psi(x) w_i psi(varrho_b) c_i (opposite of the fluid's share), with the link midpoint as
+//    lever arm;
 //  * solid nodes (repulsion enabled): between a node p of body b1 and a node q of body b2 > b1
 //    with |p - q| < r_c, f = e0 (n/r_c) (p - q)/|p - q| |(|p - q| - r_c)/r_c|^(n-1) on b1 at p
 //    and -f on b2 at q; only nodes within r_c of a higher-index body's solid radius search.
@@ -314,16 +520,17 @@ __global__ __launch_bounds__(256) void k_collide_stream(Prm<ArT<S>> p, const S *
 // partials [body * 6 + component][block], summed by the first advection sweep (k_advect), which
 // also advances the bodies.
 // waves per block of the force scan (one block per CU), sized so that the gathered link values
-// stay in registers: 12 in FP32, 8 in FP64
+// (reflected populations and link forces of every direction) stay in registers: 8 on D3Q19, 8 in
+// FP32 and 4 in FP64 on D3Q27
 template <typename T, class L>
 constexpr int force_waves() {
-    return L::Q == 19 ? (sizeof(T) == 4 ? 12 : 8) : (sizeof(T) == 4 ? 8 : 4);
+    return L::Q == 19 ? 8 : (sizeof(T) == 4 ? 8 : 4);
 }
 
 template <typename S, class L>
 __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces(Prm<ArT<S>> p, int parity,
                                                      const StepState *st, const S *__restrict__ fin,
-                                                     const S *__restrict__ fpost, const ArT<S> *__restrict__ psi,
+                                                     S *__restrict__ fpost, const ArT<S> *__restrict__ psi,
                                                      const ArT<S> *__restrict__ psi_prev,
                                                      const cell_t *__restrict__ mask,
                                                      const BodyDev *__restrict__ bodies, double *part,
@@ -355,11 +562,12 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
         int x = 0, y = 0, z = 0, idx = 0, b1 = -1;
         uint32_t nbits = 0;  // solid-neighbour bits of a fluid node
         bool fluid = false;
-        T rho = T(0), ps0 = T(0);
-        // per link i into a solid neighbour: its owner (4-bit fields) and the body-independent part
-        // of the link force, a_i = 2 f_opp(i) + G psi(x) w_i psi(x + c_i)
+        T rho = T(0), ps0 = T(0), rown = T(0), drho = T(0);
+        // per link i into a solid neighbour: its owner (4-bit fields), the reflected post-collision
+        // population fr_i = f*_i and the body-independent part of the link force, a_i = 2 f*_i +
+        // G psi(x) w_i psi(x + c_i); drho sums the moving-wall terms of the node's links
         uint32_t own[(L::Q + 7) / 8] = {};
-        T a[L::Q];
+        T a[L::Q], fr[L::Q];
         if (k < it.vol) {
             int u[3], c[3];
             it.cell(k, u, c);
@@ -383,7 +591,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                     // memory latency per link.
                     const uint32_t ib = (uint32_t)idx * (uint32_t)sizeof(T);
                     const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
-                    S fo[L::Q];  // reflected populations f_opp(i) written by k_collide_stream
+                    S fo[L::Q];  // reflected populations f*_i, in slot opp(i), written by the fluid pass
                     T pn[L::Q];  // neighbour pseudopotentials
                     sfor<L::Q>([&](auto I) {
                         constexpr int i = decltype(I)::value;
@@ -397,18 +605,20 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                     rho = sizeof(S) == 2 ? ref_density(psi_prev[idx], p.rho0) : T(0);
                     sfor<L::Q>([&](auto I) { rho += (T)ldb(fin + (long long)I * Np, is); });
                     ps0 = ldb(psi, ib);
-                    const T rown = sizeof(S) == 2 ? ref_density(ps0, p.rho0) : T(0);
+                    rown = sizeof(S) == 2 ? ref_density(ps0, p.rho0) : T(0);
                     const T gp = p.G * ps0;
                     sfor<L::Q>([&](auto I) {
                         constexpr int i = decltype(I)::value;
                         a[i] = T(0);
+                        fr[i] = T(0);
                         if constexpr (i > 0) {
                             if (nbits & (1u << i)) {
                                 const uint32_t o = (uint32_t)owner_of(mo[i]);
                                 own[i >> 3] |= o << (4 * (i & 7));
                                 touched |= 1u << o;
-                                a[i] = T(2) * pop_get<S>(fo[i], Dir<i, L>::template w<T>() * rown) +
-                                       gp * Dir<i, L>::template w<T>() * pn[i];
+                                // reflected value: f*_i, or f*_i + g_i where the fluid pass added g
+                                fr[i] = pop_get<S>(fo[i], Dir<i, L>::template w<T>() * rown);
+                                a[i] = T(2) * fr[i] + gp * Dir<i, L>::template w<T>() * pn[i];
                             }
                         }
                     });
@@ -451,10 +661,19 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                             if constexpr (Dir<i, L>::x != 0) cuw += Dir<i, L>::x * u0x;
                             if constexpr (Dir<i, L>::y != 0) cuw += Dir<i, L>::y * u0y;
                             if constexpr (Dir<i, L>::z != 0) cuw += Dir<i, L>::z * u0z;
-                            // moving-wall term g; the link carries 2 f*_i + g = 2 f_opp(i) - g to the
-                            // body plus the pseudopotential reaction, both along c_i
+                            // moving-wall term g: the reflected population becomes f*_i + g (Sec.
+                            // 3.2.2); the link carries 2 f*_i + g to the body plus the
+                            // pseudopotential reaction, both along c_i
                             const T g = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
-                            const double s = (double)(a[i] - g);
+                            double s;
+                            if constexpr (!wall_in_fluid_pass<S>()) {
+                                stb(fpost + (long long)Dir<i, L>::opp * Np, (uint32_t)idx * (uint32_t)sizeof(S),
+                                    pop_put<S>(fr[i] + g, Dir<i, L>::template w<T>() * rown));
+                                drho += g;
+                                s = (double)(a[i] + g);
+                            } else {
+                                s = (double)(a[i] - g);  // 2 (f*_i + g) - g
+                            }
                             if constexpr (Dir<i, L>::x == 1) fx += s;
                             if constexpr (Dir<i, L>::x == -1) fx -= s;
                             if constexpr (Dir<i, L>::y == 1) fy += s;
@@ -523,6 +742,12 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                 const double s = wave_sum(v[c]);
                 if (lane == 0) acc[wave][b][c] += s;
             }
+        }
+        if (!wall_in_fluid_pass<S>() && fluid && nbits) {
+            // the rest population gives back the moving-wall terms (mass correction, Sec. 3.2.2)
+            const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
+            const T f0 = pop_get<S>(ldb(fpost, is), Dir<0, L>::template w<T>() * rown);
+            stb(fpost, is, pop_put<S>(f0 - drho, Dir<0, L>::template w<T>() * rown));
         }
     }
     __syncthreads();

@@ -785,8 +785,7 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
                                              int x, int y, int z, uint32_t idx, int empty) {
     using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    // runtime loops: this runs inside the pseudopotential pass, whose register budget it must
-    // not raise (events are rare)
+    // runtime loops: events are rare, and the kernels that run this keep few registers
     const cell_t m = mask[idx];
     if (empty == 2 || (empty == 1 && (m & C_F2S))) {
         const T rr = sizeof(S) == 2 ? ref_density(psi[idx], p.rho0) : T(0);
@@ -862,39 +861,19 @@ __global__ __launch_bounds__(256) void k_post(Prm<ArT<S>> p, int parity, StepSta
                       gridDim.x * 256);
 }
 
-// Pseudopotential psi = 1 - exp(-rho/rho0) of every fluid node; a solid node carries the value
-// of its body's wetting density (Sec. 3.2.3).  Dense, one thread per cell.
-// psi_ref: the pseudopotential of the previous step (reference density of the FP16 form).
-//
-// The pass first closes the previous step's node conversions (post_events on its event list,
-// box and pseudopotential): it touches only nodes that became solid (populations this pass does
-// not read) and the neighbour bits of cell words (which it does not read either), and the
-// collision pass after it sees the result.  Without events every thread returns from it at once;
-// keeping it here saves a launch per step.
+// Closing work of a step's node conversions, launched after the conversion gather (post_events
+// on the step's event list and box): nodes that became solid are emptied (their content was
+// handed on by the gather) and the neighbour bits around every event are refreshed, before the
+// next step's fluid pass reads them.  Usual case: no node changed side and every thread returns
+// at once.  psi: the pseudopotential of this step (reference density of the FP16 form).
 template <typename S, class L>
-__global__ __launch_bounds__(256) void k_psi(Prm<ArT<S>> p, int parity, StepState *st, S *f, cell_t *mask,
-                                             uint32_t *nbw, const BodyDev *__restrict__ bodies,
-                                             const ArT<S> *__restrict__ psi_ref, ArT<S> *__restrict__ psi,
-                                             const uint32_t *__restrict__ evlist, uint32_t evcap) {
-    using T = ArT<S>;
-    const uint32_t nev = st ? st->n_events : 0u;
-    if (nev)
-        post_events<S, L>(p, st->box[parity ^ 1], nev, mask, nbw, f, psi_ref, evlist, evcap, 0,
-                          blockIdx.x * (int)blockDim.x + threadIdx.x, gridDim.x * (int)blockDim.x);
-    const int idx = xcd_block(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
-    if (idx >= p.N) return;  // flat 1-D launch: no neighbours needed
-    const cell_t m = mask[idx];
-    T out;
-    if (m & C_SOLID) {
-        out = (T)bodies[owner_of(m)].psi_s;
-    } else {
-        // the weights sum to one: rho = R + sum of the stored deviations in the FP16 form
-        T r = T(0);
-        if constexpr (sizeof(S) == 2) r = ref_density(psi_ref[idx], p.rho0);
-        sfor<L::Q>([&](auto I) { r += (T)f[(long long)I * p.Np + idx]; });
-        out = -expm1(-r * p.inv_rho0);
-    }
-    psi[idx] = out;
+__global__ __launch_bounds__(256) void k_close_events(Prm<ArT<S>> p, int parity, StepState *st, S *f, cell_t *mask,
+                                                      uint32_t *nbw, const ArT<S> *__restrict__ psi,
+                                                      const uint32_t *__restrict__ evlist, uint32_t evcap) {
+    const uint32_t nev = st->n_events;
+    if (!nev) return;
+    post_events<S, L>(p, st->box[parity], nev, mask, nbw, f, psi, evlist, evcap, 0, blockIdx.x * 256 + threadIdx.x,
+                      gridDim.x * 256);
 }
 
 // ---- initialisation and read-out helpers ------------------------------------------------------

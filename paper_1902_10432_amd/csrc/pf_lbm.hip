@@ -59,9 +59,9 @@ struct pf_lbm {
     int dense_blocks = 0, box_blocks = 1;
     int box_grid = 1, force_grid = 1;  // grids of the box kernels and of the force scan
     int cgrid = 1;  // classification partials written per step (grid of the phase update)
-    // launch shapes that leave the arithmetic unchanged (pf_lbm_autotune): rows of the collide
-    // block (64 x rows threads) and the block size of the pseudopotential kernel
-    int rows = 4, psi_bs = 256;
+    // tile shape of the fluid pass, which leaves the arithmetic unchanged (pf_lbm_autotune): rows
+    // of the 64-wide tile (block of 64 x fluid_ty threads) and planes per z-chunk
+    int fluid_ty = 8, fluid_tz = 32;
     long long steps = 0;
     std::vector<double> sigma;
     std::string err;
@@ -263,6 +263,46 @@ Prm<T> make_prm(const pf_lbm *h) {
     return p;
 }
 
+// Tile rows the fluid pass is built for with storage S on lattice Lat (its LDS stays within 64 KB:
+// FP64 populations take 4-row tiles, the others 4 or 8).
+template <typename S, class Lat>
+bool fluid_ty_ok(int ty) {
+    return ty == 4 || (ty == 8 && fluid_tile_fits<S, Lat, 2>());
+}
+
+// planes per z-chunk: the longest power of two in [4, 64] that still gives the grid 1024 blocks
+// (four per CU), 4 when none does
+int default_tz(int nx, int ny, int nz, int ty) {
+    const long long tiles = (long long)((nx + 63) / 64) * ((ny + ty - 1) / ty);
+    int tz = 64;
+    while (tz > 4 && tiles * ((nz + tz - 1) / tz) < 1024) tz /= 2;
+    return tz;
+}
+
+template <typename S, class Lat, int RPT>
+void launch_fluid_rpt(pf_lbm *h, const Prm<ArT<S>> &p, const S *fc, S *fn, ArT<S> *psi, const ArT<S> *psi_prev,
+                      const cell_t *mask, BodyDev *cur, int par, StepState *st, const ClassifyPart *cpart,
+                      const uint32_t *nbw) {
+    if constexpr (fluid_tile_fits<S, Lat, RPT>()) {
+        constexpr int TY = FLUID_WAVES * RPT;
+        const int tz = h->fluid_tz;
+        const unsigned tiles = (unsigned)(((h->cfg.nx + 63) / 64) * ((h->cfg.ny + TY - 1) / TY));
+        const unsigned chunks = (unsigned)((h->cfg.nz + tz - 1) / tz);
+        k_collide_stream<S, Lat, RPT><<<dim3(tiles * chunks), dim3(64 * FLUID_WAVES), 0, h->stream>>>(
+            p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, h->cgrid, nbw, tz);
+    }
+}
+
+template <typename S, class Lat>
+void launch_fluid(pf_lbm *h, const Prm<ArT<S>> &p, const S *fc, S *fn, ArT<S> *psi, const ArT<S> *psi_prev,
+                  const cell_t *mask, BodyDev *cur, int par, StepState *st, const ClassifyPart *cpart,
+                  const uint32_t *nbw) {
+    if (h->fluid_ty == 8)
+        launch_fluid_rpt<S, Lat, 2>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, nbw);
+    else
+        launch_fluid_rpt<S, Lat, 1>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, nbw);
+}
+
 template <typename T>
 T *fbuf(pf_lbm *h, int which) {
     return (T *)(h->ws + (which ? h->L.fB : h->L.fA));
@@ -332,7 +372,7 @@ int enqueue_step(pf_lbm *h, double *parts = nullptr) {
     // per-block force partials: the workspace's, or the caller-supplied static copy
     double *pforce = parts ? parts : (double *)(h->ws + h->L.pforce);
     ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
-    const dim3 gd((unsigned)((h->N + h->psi_bs - 1) / h->psi_bs)), b(256);
+    const dim3 b(256);
     hipStream_t s = h->stream;
     hipEvent_t *ev = nullptr;
     if (h->timing && h->timed < 4096) {
@@ -348,12 +388,8 @@ int enqueue_step(pf_lbm *h, double *parts = nullptr) {
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[0], s));
     uint32_t *evlist = (uint32_t *)(h->ws + h->L.evlist);
-    k_psi<S, Lat><<<gd, dim3(h->psi_bs), 0, s>>>(p, par, h->nb > 0 ? st : nullptr, fc, mask, nbw, cur, psi_prev, psi,
-                                                 evlist, EV_CAP);
     if (ev) HIPCHK(h, hipEventRecord(ev[1], s));
-    k_collide_stream<S, Lat><<<dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + h->rows - 1) / h->rows, h->cfg.nz),
-                               dim3(64, h->rows), 0, s>>>(
-        p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, h->cgrid, nbw);
+    launch_fluid<S, Lat>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, h->nb > 0 ? cpart : nullptr, nbw);
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
@@ -362,10 +398,11 @@ int enqueue_step(pf_lbm *h, double *parts = nullptr) {
         // one kernel per sweep; the phase fields end in buffer A every step
         launch_advect<T>(h, p, par, st, cur, next, pforce, fbk, phiA, phiB);
         launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
-        // conversion gather: usually returns at once (no node changed side), so a small grid; the
-        // next step's pseudopotential pass closes the conversions
+        // conversion gather, then its closing pass: both usually return at once (no node changed
+        // side), so a small grid
         const dim3 ge(std::min(h->box_grid, 64));
         k_convert_gather<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP);
+        k_close_events<S, Lat><<<ge, b, 0, s>>>(p, par, st, fn, mask, nbw, psi, evlist, EV_CAP);
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[3], s));
     HIPCHK(h, hipGetLastError());
@@ -545,6 +582,8 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     h->box_grid = box_grid;
     h->force_grid = force_grid;
     h->cgrid = cgrid;
+    h->fluid_ty = cfg->precision == PF_LBM_FP64 ? 4 : 8;
+    h->fluid_tz = default_tz(cfg->nx, cfg->ny, cfg->nz, h->fluid_ty);
     const int np1 = n_bodies + 1;
     h->sigma.assign((size_t)np1 * np1, 0.0);
     for (int a = 0; a < np1; ++a)
@@ -847,16 +886,24 @@ int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3) {
     if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
     if (steps_per_candidate < 2) return fail(h, PF_LBM_EINVAL, "steps_per_candidate must be >= 2");
     if (h->timing) return fail(h, PF_LBM_EINVAL, "autotune while timing is on");
-    const int rows_c[3] = {1, 2, 4}, bs_c[2] = {128, 256};
+    const int ty_c[2] = {4, 8}, tz_c[5] = {4, 8, 16, 32, 64};
+    auto ty_ok = [&](int ty) {
+        if (h->q == 27)
+            return h->prec == PF_LBM_FP64 ? fluid_ty_ok<double, D3Q27>(ty)
+                   : h->prec == PF_LBM_FP32 ? fluid_ty_ok<float, D3Q27>(ty) : fluid_ty_ok<half_t, D3Q27>(ty);
+        return h->prec == PF_LBM_FP64 ? fluid_ty_ok<double, D3Q19>(ty)
+               : h->prec == PF_LBM_FP32 ? fluid_ty_ok<float, D3Q19>(ty) : fluid_ty_ok<half_t, D3Q19>(ty);
+    };
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
     double best = 1e300;
-    int best_rows = h->rows, best_bs = h->psi_bs;
-    for (int r : rows_c)
-        for (int bs : bs_c) {
-            h->rows = r;
-            h->psi_bs = bs;
+    int best_ty = h->fluid_ty, best_tz = h->fluid_tz;
+    for (int ty : ty_c)
+        for (int tz : tz_c) {
+            if (!ty_ok(ty) || (tz > h->cfg.nz && tz != tz_c[0])) continue;
+            h->fluid_ty = ty;
+            h->fluid_tz = tz;
             // one untimed step with the candidate, then the timed ones (launched one by one)
             int rc = eager_step(h);
             if (rc == PF_LBM_OK) {
@@ -874,21 +921,38 @@ int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3) {
             HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
             if (ms < best) {
                 best = ms;
-                best_rows = r;
-                best_bs = bs;
+                best_ty = ty;
+                best_tz = tz;
             }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    h->rows = best_rows;
-    h->psi_bs = best_bs;
+    h->fluid_ty = best_ty;
+    h->fluid_tz = best_tz;
     // the captured steps used the old shapes: capture again on the next pf_lbm_step
     drop_graphs(h);
     if (out3) {
-        out3[0] = best_rows;
-        out3[1] = best_bs;
+        out3[0] = best_ty;
+        out3[1] = best_tz;
         out3[2] = best / steps_per_candidate;
     }
+    return PF_LBM_OK;
+}
+
+int pf_lbm_set_tile(pf_lbm *h, int32_t rows, int32_t planes) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    bool ok;
+    if (h->q == 27)
+        ok = h->prec == PF_LBM_FP64 ? fluid_ty_ok<double, D3Q27>(rows)
+             : h->prec == PF_LBM_FP32 ? fluid_ty_ok<float, D3Q27>(rows) : fluid_ty_ok<half_t, D3Q27>(rows);
+    else
+        ok = h->prec == PF_LBM_FP64 ? fluid_ty_ok<double, D3Q19>(rows)
+             : h->prec == PF_LBM_FP32 ? fluid_ty_ok<float, D3Q19>(rows) : fluid_ty_ok<half_t, D3Q19>(rows);
+    if (!ok) return fail(h, PF_LBM_EUNSUPPORTED, "tile of %d rows not built for this precision and lattice", rows);
+    if (planes < 1 || planes > 4096) return fail(h, PF_LBM_EINVAL, "planes per chunk must lie in [1, 4096]");
+    h->fluid_ty = rows;
+    h->fluid_tz = planes;
+    drop_graphs(h);
     return PF_LBM_OK;
 }
 

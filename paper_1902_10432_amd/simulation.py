@@ -137,7 +137,11 @@ class Simulation:
         """Pick the fastest result-invariant launch shapes (advances the simulation)."""
         rc, out = B.pf_lbm_autotune(self._h, steps_per_candidate)
         self._check(rc)
-        return {"rows": int(out[0]), "psi_block": int(out[1]), "ms_per_step": out[2]}
+        return {"tile_rows": int(out[0]), "chunk_planes": int(out[1]), "ms_per_step": out[2]}
+
+    def set_tile(self, rows: int, planes: int) -> None:
+        """Tile shape of the fluid pass: 64 x rows nodes, z-chunks of planes planes."""
+        self._check(B.load_library().pf_lbm_set_tile(self._h, int(rows), int(planes)))
 
     def diag(self) -> dict:
         rc, out = B.pf_lbm_diagnostics(self._h)

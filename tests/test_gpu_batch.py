@@ -75,8 +75,10 @@ def test_autotune_changes_launch_shapes_only(torch_cuda):
     tuned, plain = _sim(w), _sim(w)
     t = tuned.autotune(4)
     _print(f"  autotune: {t}")
-    assert t["rows"] in (1, 2, 4) and t["psi_block"] in (128, 256)
-    plain.step(6 * (1 + 4))      # the steps the six candidates took
+    assert t["tile_rows"] in (4, 8) and t["chunk_planes"] in (4, 8, 16, 32, 64)
+    taken = tuned.diag()["step"]  # the steps the candidates took (1 + 4 each)
+    assert taken % 5 == 0 and taken >= 5
+    plain.step(taken)
     tuned.step(20)
     plain.step(20)
     for x, y in zip(_state(tuned), _state(plain)):
