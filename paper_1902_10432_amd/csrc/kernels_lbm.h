@@ -229,11 +229,17 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
                 if (!(solid_dirs & (1u << i))) {
                     stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
                 } else {
+                    // the FP16 form's collision arithmetic is FP32: the lever arm about the body
+                    // centre (minimum image, FP64) and the wall velocity at the link midpoint in FP32
                     const BodyDev &Bd = bodies[owner_of(mask[ne.template at<i>(idx)])];
-                    double uwx, uwy, uwz;
-                    wall_velocity(p, Bd, x + 0.5 * Dir<i, L>::x, y + 0.5 * Dir<i, L>::y, z + 0.5 * Dir<i, L>::z, uwx, uwy, uwz);
-                    const double cuw = Dir<i, L>::x * uwx + Dir<i, L>::y * uwy + Dir<i, L>::z * uwz;
-                    const T gw = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
+                    const T rx = (T)mimg_r(x - Bd.X[0], nx, p.inv_n[0]) + T(0.5 * Dir<i, L>::x),
+                            ry = (T)mimg_r(y - Bd.X[1], ny, p.inv_n[1]) + T(0.5 * Dir<i, L>::y),
+                            rz = (T)mimg_r(z - Bd.X[2], nz, p.inv_n[2]) + T(0.5 * Dir<i, L>::z);
+                    const T wx = (T)Bd.W[0], wy = (T)Bd.W[1], wz = (T)Bd.W[2];
+                    const T uwx = (T)Bd.V[0] + (wy * rz - wz * ry), uwy = (T)Bd.V[1] + (wz * rx - wx * rz),
+                            uwz = (T)Bd.V[2] + (wx * ry - wy * rx);
+                    const T cuw = T(Dir<i, L>::x) * uwx + T(Dir<i, L>::y) * uwy + T(Dir<i, L>::z) * uwz;
+                    const T gw = T(-6.0 * Dir<i, L>::template w<double>()) * cuw * rho;
                     stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
                     drho += gw;
                 }
@@ -256,17 +262,22 @@ struct FluidLds {
     S hpop[NB][L::Q][NH];
     cell_t hmask[NB][NH];
 };
-// a block is four waves; each thread owns RPT rows of the tile (TY = 4 RPT)
-constexpr int FLUID_WAVES = 4;
-template <typename S, class L, int RPT>
+// Tile shapes of the fluid pass: TY rows of 64 nodes, W waves per block, each thread owning
+// RPT = TY / W rows.  LDS stays within 80 KB so that two blocks share a CU (160 KB).
+template <int TY>
+struct FluidShape {
+    static constexpr int W = TY <= 4 ? 4 : 8, RPT = TY / W;
+};
+constexpr size_t FLUID_LDS_MAX = 80 * 1024;
+template <typename S, class L, int TY>
 constexpr bool fluid_tile_fits() {
-    return sizeof(FluidLds<S, L, FLUID_WAVES * RPT, false>) <= 65536;
+    return sizeof(FluidLds<S, L, TY, false>) <= FLUID_LDS_MAX;
 }
 // direct loads into LDS move one dword per lane (a shorter element would still take a dword slot
 // of LDS per lane): FP32 populations only
-template <typename S, class L, int RPT>
+template <typename S, class L, int TY>
 constexpr bool fluid_halo_dma() {
-    return sizeof(S) == 4 && sizeof(FluidLds<S, L, FLUID_WAVES * RPT, true>) <= 65536;
+    return sizeof(S) == 4 && sizeof(FluidLds<S, L, TY, true>) <= FLUID_LDS_MAX;
 }
 
 // one node's inputs of one plane: its stored populations, cell word and (FP16) previous psi
@@ -291,10 +302,10 @@ __device__ __forceinline__ ArT<S> node_psi_of(const Prm<ArT<S>> &p, const BodyDe
     return -expm1(-r * p.inv_rho0);
 }
 
-// The fluid pass (see above).  Launch: 256 threads per block (four waves, one x-row of 64 nodes
-// per wave and row set), tiles of 64 x TY nodes with TY = 4 RPT (thread (tx, w) owns rows w,
-// w + 4, ..), a 1-D grid of ceil(nx/64) * ceil(ny/TY) * ceil(nz/tz) blocks; blocks are ordered so
-// that each XCD holds a contiguous run of tiles (a z-chunk of neighbouring tiles shares an L2).
+// The fluid pass (see above).  Launch: 64 W threads per block (W waves, one x-row of 64 nodes
+// per wave and row set), tiles of 64 x TY nodes (thread (tx, w) owns rows w, w + W, ..), a 1-D
+// grid of ceil(nx/64) * ceil(ny/TY) * ceil(nz/tz) blocks; blocks are ordered so that each XCD
+// holds a contiguous run of tiles (a z-chunk of neighbouring tiles shares an L2).
 //
 // Software pipeline along z: while plane z is collided, the tile's own populations of plane z + 2
 // are in flight into registers and (DMA) the halo's straight into LDS; at the top of the next
@@ -304,8 +315,8 @@ __device__ __forceinline__ ArT<S> node_psi_of(const Prm<ArT<S>> &p, const BodyDe
 // With bodies, the first block also publishes the step's box, solid radii, volume terms and event
 // flag from the previous reclassification (publish_step_state) before its own cells: that short
 // reduction chain then hides behind the longest pass of the step instead of costing a launch.
-template <typename S, class L, int RPT>
-__global__ __launch_bounds__(64 * FLUID_WAVES) void k_collide_stream(Prm<ArT<S>> p, const S *__restrict__ fin,
+template <typename S, class L, int TY>
+__global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<ArT<S>> p, const S *__restrict__ fin,
                                                                      S *__restrict__ fout, ArT<S> *__restrict__ psi,
                                                                      const ArT<S> *__restrict__ psi_prev,
                                                                      const cell_t *__restrict__ mask, BodyDev *bodies,
@@ -313,9 +324,9 @@ __global__ __launch_bounds__(64 * FLUID_WAVES) void k_collide_stream(Prm<ArT<S>>
                                                                      const ClassifyPart *__restrict__ cpart, int cblk,
                                                                      const uint32_t *__restrict__ nbw, int tz) {
     using T = ArT<S>;
-    constexpr int W = FLUID_WAVES, TY = W * RPT;
-    constexpr bool DMA = fluid_halo_dma<S, L, RPT>();
-    static_assert(fluid_tile_fits<S, L, RPT>(), "LDS of the fluid pass above 64 KB");
+    constexpr int W = FluidShape<TY>::W, RPT = FluidShape<TY>::RPT;
+    constexpr bool DMA = fluid_halo_dma<S, L, TY>();
+    static_assert(fluid_tile_fits<S, L, TY>(), "LDS of the fluid pass above its budget");
     __shared__ FluidLds<S, L, TY, DMA> lds;
     constexpr bool H = sizeof(S) == 2;
     const int tid = (int)threadIdx.x, tx = tid & 63, wv = tid >> 6;

@@ -263,12 +263,13 @@ Prm<T> make_prm(const pf_lbm *h) {
     return p;
 }
 
-// Tile rows the fluid pass is built for with storage S on lattice Lat (its LDS stays within 64 KB:
-// FP64 populations take 4-row tiles, the others 4 or 8).
+// Tile rows the fluid pass is built for with storage S on lattice Lat (4, 8 or 16, as its LDS
+// budget allows)
 template <typename S, class Lat>
 bool fluid_ty_ok(int ty) {
-    return ty == 4 || (ty == 8 && fluid_tile_fits<S, Lat, 2>());
+    return ty == 4 || (ty == 8 && fluid_tile_fits<S, Lat, 8>()) || (ty == 16 && fluid_tile_fits<S, Lat, 16>());
 }
+
 
 // planes per z-chunk: the longest power of two in [4, 64] that still gives the grid 1024 blocks
 // (four per CU), 4 when none does
@@ -279,16 +280,15 @@ int default_tz(int nx, int ny, int nz, int ty) {
     return tz;
 }
 
-template <typename S, class Lat, int RPT>
-void launch_fluid_rpt(pf_lbm *h, const Prm<ArT<S>> &p, const S *fc, S *fn, ArT<S> *psi, const ArT<S> *psi_prev,
-                      const cell_t *mask, BodyDev *cur, int par, StepState *st, const ClassifyPart *cpart,
-                      const uint32_t *nbw) {
-    if constexpr (fluid_tile_fits<S, Lat, RPT>()) {
-        constexpr int TY = FLUID_WAVES * RPT;
+template <typename S, class Lat, int TY>
+void launch_fluid_ty(pf_lbm *h, const Prm<ArT<S>> &p, const S *fc, S *fn, ArT<S> *psi, const ArT<S> *psi_prev,
+                     const cell_t *mask, BodyDev *cur, int par, StepState *st, const ClassifyPart *cpart,
+                     const uint32_t *nbw) {
+    if constexpr (fluid_tile_fits<S, Lat, TY>()) {
         const int tz = h->fluid_tz;
         const unsigned tiles = (unsigned)(((h->cfg.nx + 63) / 64) * ((h->cfg.ny + TY - 1) / TY));
         const unsigned chunks = (unsigned)((h->cfg.nz + tz - 1) / tz);
-        k_collide_stream<S, Lat, RPT><<<dim3(tiles * chunks), dim3(64 * FLUID_WAVES), 0, h->stream>>>(
+        k_collide_stream<S, Lat, TY><<<dim3(tiles * chunks), dim3(64 * FluidShape<TY>::W), 0, h->stream>>>(
             p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, h->cgrid, nbw, tz);
     }
 }
@@ -297,10 +297,12 @@ template <typename S, class Lat>
 void launch_fluid(pf_lbm *h, const Prm<ArT<S>> &p, const S *fc, S *fn, ArT<S> *psi, const ArT<S> *psi_prev,
                   const cell_t *mask, BodyDev *cur, int par, StepState *st, const ClassifyPart *cpart,
                   const uint32_t *nbw) {
-    if (h->fluid_ty == 8)
-        launch_fluid_rpt<S, Lat, 2>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, nbw);
+    if (h->fluid_ty == 16)
+        launch_fluid_ty<S, Lat, 16>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, nbw);
+    else if (h->fluid_ty == 8)
+        launch_fluid_ty<S, Lat, 8>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, nbw);
     else
-        launch_fluid_rpt<S, Lat, 1>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, nbw);
+        launch_fluid_ty<S, Lat, 4>(h, p, fc, fn, psi, psi_prev, mask, cur, par, st, cpart, nbw);
 }
 
 template <typename T>
@@ -886,7 +888,7 @@ int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3) {
     if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
     if (steps_per_candidate < 2) return fail(h, PF_LBM_EINVAL, "steps_per_candidate must be >= 2");
     if (h->timing) return fail(h, PF_LBM_EINVAL, "autotune while timing is on");
-    const int ty_c[2] = {4, 8}, tz_c[5] = {4, 8, 16, 32, 64};
+    const int ty_c[3] = {4, 8, 16}, tz_c[5] = {4, 8, 16, 32, 64};
     auto ty_ok = [&](int ty) {
         if (h->q == 27)
             return h->prec == PF_LBM_FP64 ? fluid_ty_ok<double, D3Q27>(ty)
