@@ -154,51 +154,131 @@ def oracle_timing() -> int:
     return 0
 
 
+def force_errors(ws, hist, hist64, steps: int) -> dict:
+    """Per-instance force error of one sweep against its FP64 twin: |F - F_fp64| over
+    max(|F_fp64|, pi sigma R_min), on the mean of the last 500 steps and per step over the first
+    200; max, median, the count above 1e-3 and the worst instances."""
+    sigma, window, early = 3.3e-2, min(500, steps), min(200, steps)
+    late, first = [], []
+    for w, h, h64 in zip(ws, hist, hist64):
+        scale_r = math.pi * sigma * min(w.meta["radii"])
+        f, f64 = h[-window:, :, :3].mean(axis=0), h64[-window:, :, :3].mean(axis=0)
+        late.append(float(np.abs(f - f64).max() / max(np.abs(f64).max(), scale_r)))
+        d = np.abs(h[:early, :, :3] - h64[:early, :, :3]).max(axis=(1, 2))
+        sc = np.maximum(np.abs(h64[:early, :, :3]).max(axis=(1, 2)), scale_r)
+        first.append(float((d / sc).max()))
+
+    def stats(e):
+        worst = np.argsort(e)[::-1][:3]
+        return {"max": float(f"{max(e):.3g}"), "median": float(f"{np.median(e):.3g}"),
+                "over_1e-3": int(sum(x > 1e-3 for x in e)),
+                "worst": [[int(k), float(f"{e[k]:.3g}")] for k in worst]}
+
+    return {f"mean_of_last_{window}_steps": stats(late), f"per_step_first_{early}_steps": stats(first)}
+
+
 def batched_sweep(args) -> int:
-    """The sweep of uneven two-sphere bridges (grids 48^3..128^3, seeded): every instance stepped
-    alone, one after the other, against all instances stepped together by pf_lbm_step_batch.
-    Prints one JSON line with both throughputs (MLUPS over all instances' nodes)."""
+    """The sweep of uneven two-sphere bridges (grids 48^3..128^3, seeded; config 4), stepped three
+    ways over the same number of steps: every instance alone, one after the other; all instances
+    by pf_lbm_step_batch (launches interleaved over the instances' streams); all instances as one
+    captured HIP graph (pf_lbm_batch_*).  Each instance's fluid-pass tile is autotuned first
+    (unless --no-autotune).  The same sweep in FP64 gives each instance's force error, as
+    |F - F_fp64| over max(|F_fp64|, pi sigma R_min), averaged over the last 500 steps (the
+    instantaneous force carries the period-2 staggered mode) and per step over the first 200.
+    The error is taken twice: with the spheres held at their gap (the field solve of the force
+    table: precision alone separates the two runs) and with the spheres moving (node conversions
+    a step apart in the two precisions let the trajectories part, so the late window measures
+    that divergence, not the precision of one solve).  Prints one JSON line (MLUPS over all
+    instances' nodes)."""
     import torch
 
-    from paper_1902_10432_amd.simulation import Simulation, step_batch
+    from paper_1902_10432_amd.simulation import Batch, Simulation, step_batch
     from pflbm_inputs import bridge_sweep
 
+    steps = args.batched_steps
     t0 = time.perf_counter()
     ws = bridge_sweep(args.batched, seed=0)
     cells = sum(w.cells for w in ws)
     log(f"{len(ws)} instances, {cells / 1e6:.1f} M nodes, generated in {time.perf_counter() - t0:.1f} s")
-    sims = [Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=args.precision) for w in ws]
-    tuned = None
-    if args.autotune:
-        tuned = [s.autotune(4) for s in sims]
-    # warm-up of both paths (each captures its graphs: step pairs for the batch, runs of 32 steps
-    # for an instance stepped alone)
-    step_batch(sims, args.warmup)
+
+    def make(prec):
+        return [Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=prec) for w in ws]
+
+    sims = make(args.precision)
+    tiles = None
+    if not args.no_autotune:
+        tiles = [s.autotune(4) for s in sims]
+        log("autotuned tiles: " + json.dumps(sorted({(t["tile_rows"], t["chunk_planes"]) for t in tiles})))
+    graph = Batch(sims, graph_steps=args.graph_steps)
+    # warm-up of every path (each captures its graphs)
+    step_batch(sims, 2)
+    graph.step(args.graph_steps)
     for s in sims:
-        s.step(max(args.warmup, 32))
+        s.step(32)
     torch.cuda.synchronize()
     # sequential: one instance at a time
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     seq_ms = 0.0
     for s in sims:
         ev[0].record(s.stream)
-        s.step(args.steps)
+        s.step(steps)
         ev[1].record(s.stream)
         torch.cuda.synchronize()
         seq_ms += ev[0].elapsed_time(ev[1])
-    # batched
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step_batch(sims, args.steps)
-    torch.cuda.synchronize()
-    bat_ms = (time.perf_counter() - t1) * 1e3
-    seq = cells * args.steps / (seq_ms / 1e3) / 1e6
-    bat = cells * args.steps / (bat_ms / 1e3) / 1e6
-    ok = all(np.isfinite(s.force_history(args.steps)).all() for s in sims)
-    out = {"metric": "batched uneven bridge sweep MLUPS", "value": round(bat, 2), "unit": "MLUPS",
-           "sequential": round(seq, 2), "vs_sequential": round(bat / seq, 3), "instances": len(ws),
-           "cells": cells, "steps": args.steps, "warmup": args.warmup, "precision": args.precision,
-           "autotuned": tuned is not None, "finite_force_histories": bool(ok), "data": "synthetic"}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) * 1e3
+
+    rr_ms = timed(lambda: step_batch(sims, steps))
+    gr_ms = timed(lambda: graph.step(steps))
+    rate = lambda ms: cells * steps / (ms / 1e3) / 1e6
+    seq, rr, gr = rate(seq_ms), rate(rr_ms), rate(gr_ms)
+    ok = all(np.isfinite(s.force_history(steps)).all() for s in sims)
+    pop, arith = FORMS[args.precision]
+    achieved = gr * 1e6 * step_bytes_per_cell(pop, arith) / 1e9
+    out = {"metric": "batched uneven bridge sweep MLUPS (one captured graph)", "value": round(gr, 2),
+           "unit": "MLUPS", "n_gpus": 1, "steps": steps, "higher_is_better": True,
+           "sequential": round(seq, 2), "round_robin_streams": round(rr, 2),
+           "vs_sequential": round(gr / seq, 3), "round_robin_vs_sequential": round(rr / seq, 3),
+           "instances": len(ws), "cells": cells, "graph_steps": args.graph_steps, "precision": args.precision,
+           "tiles": None if tiles is None else sorted({f"{t['tile_rows']}x{t['chunk_planes']}" for t in tiles}),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "whole step, all instances (kernels of different instances overlap)",
+                        "bytes_per_cell_step": step_bytes_per_cell(pop, arith)},
+           "finite_force_histories": bool(ok), "data": "synthetic",
+           "config": {"workload": f"bridge_sweep seed 0: {len(ws)} two-sphere instances, grids 48..128 per axis",
+                      "cells": cells}}
+    if not args.no_fp64_check and args.precision != "fp64":
+        # fresh sweeps of `steps` steps each through the batch graph, in the bench's precision and
+        # in FP64 (default tiles: the arithmetic does not depend on them)
+        graph.close()
+        for s in sims:
+            s.close()
+        del graph, sims
+        torch.cuda.empty_cache()
+        out["force_error_vs_fp64"] = {}
+        for label, fixed in (("spheres_fixed", True), ("spheres_moving", False)):
+            wk = bridge_sweep(args.batched, seed=0, fixed=fixed)
+            hists = {}
+            for prec in (args.precision, "fp64"):
+                run = [Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=prec) for w in wk]
+                bg = Batch(run, graph_steps=args.graph_steps)
+                bg.step(steps)
+                hists[prec] = [r.force_history(steps) for r in run]
+                bg.close()
+                for r in run:
+                    r.close()
+                del bg, run
+                torch.cuda.empty_cache()
+            out["force_error_vs_fp64"][label] = force_errors(wk, hists[args.precision], hists["fp64"], steps)
+            log(f"force error vs fp64, {label}: {json.dumps(out['force_error_vs_fp64'][label])}")
+        out["force_error_vs_fp64"]["definition"] = (
+            f"|F - F_fp64| / max(|F_fp64|, pi sigma R_min) per instance over {steps} steps")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -304,7 +384,9 @@ def main() -> int:
                     help="only run plain copies of MIB MiB (profiler counter calibration)")
     ap.add_argument("--batched", type=int, default=0, metavar="N",
                     help="only the batched sweep of N uneven two-sphere instances against sequential runs")
-    ap.add_argument("--autotune", action="store_true", help="autotune each instance of the batched sweep")
+    ap.add_argument("--batched-steps", type=int, default=2000, help="steps of each path of the batched sweep")
+    ap.add_argument("--graph-steps", type=int, default=4, help="steps per replay of the batch graph (even)")
+    ap.add_argument("--no-fp64-check", action="store_true", help="skip the FP64 twin of the batched sweep")
     ap.add_argument("--surrogate", action="store_true",
                     help="only the bridge-force surrogate: sweep, GPU training, 1000-sphere run with re-solves")
     ap.add_argument("--surrogate-seeds", type=int, default=4, help="64-bridge sweeps of training data")

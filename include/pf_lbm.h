@@ -195,6 +195,22 @@ int pf_lbm_force_history(pf_lbm *h, int32_t max_steps, double *out, int32_t *n_o
  * Returns the first error (its message on that handle). */
 int pf_lbm_step_batch(pf_lbm *const *handles, int32_t n, int32_t n_steps);
 
+/* A batch of independent simulations stepped as one HIP graph: graph_steps (even, >= 2) steps of
+ * every instance are captured once -- a fork from the first instance's stream, each instance's
+ * kernels on its own stream, a join back -- and replayed as one launch on the first instance's
+ * stream, ordered after work already queued on the instances' streams and before later work on
+ * them.  The handles (distinct, each bound to a stream of its own, not timing) stay owned by the
+ * caller and must outlive the batch; per instance the result is bit for bit that of pf_lbm_step.
+ * The graph is captured again when an instance's step parity differs from that at capture (it
+ * was stepped on its own); steps beyond a multiple of graph_steps go through pf_lbm_step_batch.
+ * Errors: PF_LBM_EINVAL, PF_LBM_ENOMEM, PF_LBM_EDEVICE (message from pf_lbm_batch_last_error;
+ * of pf_lbm_batch_create: pf_lbm_last_error(NULL)). */
+typedef struct pf_lbm_batch pf_lbm_batch;
+int pf_lbm_batch_create(pf_lbm *const *handles, int32_t n, int32_t graph_steps, pf_lbm_batch **out);
+int pf_lbm_batch_step(pf_lbm_batch *b, int32_t n_steps);
+void pf_lbm_batch_destroy(pf_lbm_batch *b);
+const char *pf_lbm_batch_last_error(const pf_lbm_batch *b);
+
 /* Autotuner of the tile shape of the fluid pass, which leaves the arithmetic unchanged: tiles of
  * 64 x 4 or 64 x 8 nodes (FP64 populations: 64 x 4) marching z-chunks of 4, 8, 16, 32 or 64
  * planes.  Each candidate runs 1 + steps_per_candidate steps of the simulation itself (the state

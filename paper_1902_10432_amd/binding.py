@@ -41,7 +41,8 @@ PF_LBM_DST_F32 = 1
 
 EXPORTED = ("pf_lbm_init", "pf_lbm_step", "pf_lbm_step_noalloc", "pf_lbm_forces", "pf_lbm_fields", "pf_lbm_diagnostics",
             "pf_lbm_timing", "pf_lbm_force_history", "pf_lbm_step_batch", "pf_lbm_autotune", "pf_lbm_set_tile", "pf_lbm_destroy",
-            "pf_lbm_last_error")
+            "pf_lbm_last_error", "pf_lbm_batch_create", "pf_lbm_batch_step", "pf_lbm_batch_destroy",
+            "pf_lbm_batch_last_error")
 
 
 class PfLbmConfig(C.Structure):
@@ -106,6 +107,14 @@ def load_library():
     lib.pf_lbm_step_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_int32]
     lib.pf_lbm_autotune.restype = C.c_int
     lib.pf_lbm_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
+    lib.pf_lbm_batch_create.restype = C.c_int
+    lib.pf_lbm_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+    lib.pf_lbm_batch_step.restype = C.c_int
+    lib.pf_lbm_batch_step.argtypes = [C.c_void_p, C.c_int32]
+    lib.pf_lbm_batch_destroy.restype = None
+    lib.pf_lbm_batch_destroy.argtypes = [C.c_void_p]
+    lib.pf_lbm_batch_last_error.restype = C.c_char_p
+    lib.pf_lbm_batch_last_error.argtypes = [C.c_void_p]
     lib.pf_lbm_set_tile.restype = C.c_int
     lib.pf_lbm_set_tile.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.pf_lbm_destroy.restype = None
@@ -173,6 +182,27 @@ def pf_lbm_force_history(h, max_steps: int, n_bodies: int):
     n = C.c_int32(0)
     rc = load_library().pf_lbm_force_history(h, int(max_steps), _dptr(out), C.byref(n))
     return rc, out[: n.value * n_bodies * 6].reshape(n.value, n_bodies, 6)
+
+
+def pf_lbm_batch_create(handles, graph_steps: int):
+    """Returns (status, batch handle)."""
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    out = C.c_void_p()
+    rc = load_library().pf_lbm_batch_create(arr, len(handles), int(graph_steps), C.byref(out))
+    return rc, out
+
+
+def pf_lbm_batch_step(batch, n_steps: int) -> int:
+    return load_library().pf_lbm_batch_step(batch, int(n_steps))
+
+
+def pf_lbm_batch_destroy(batch) -> None:
+    load_library().pf_lbm_batch_destroy(batch)
+
+
+def pf_lbm_batch_last_error(batch) -> str:
+    m = load_library().pf_lbm_batch_last_error(batch)
+    return m.decode() if m else ""
 
 
 def pf_lbm_step_batch(handles, n_steps: int) -> int:

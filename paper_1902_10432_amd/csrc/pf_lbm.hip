@@ -884,6 +884,146 @@ int pf_lbm_step_batch(pf_lbm *const *handles, int32_t n, int32_t n_steps) {
     return PF_LBM_OK;
 }
 
+}  // extern "C"
+
+// A batch: the steps of many instances captured as one HIP graph (a fork from the first
+// instance's stream, each instance's kernels on its own stream, a join back), replayed as one
+// launch.
+struct pf_lbm_batch {
+    std::vector<pf_lbm *> hs;
+    int graph_steps = 2;
+    hipGraphExec_t graph = nullptr;
+    std::vector<int> parity;              // step parity of each instance at capture
+    std::vector<hipEvent_t> ev;           // one per instance (fork, join and ordering)
+    std::string err;
+};
+
+namespace {
+
+int bfail(pf_lbm_batch *b, int code, const std::string &msg) {
+    b->err = msg;
+    return code;
+}
+
+#define BCHK(b, call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return bfail((b), PF_LBM_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// capture graph_steps steps of every instance into one executable graph
+int batch_capture(pf_lbm_batch *b) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    hipStream_t origin = b->hs[0]->stream;
+    const int n = (int)b->hs.size();
+    std::vector<long long> s0(n);
+    for (int i = 0; i < n; ++i) s0[i] = b->hs[i]->steps;
+    BCHK(b, hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed));
+    int rc = PF_LBM_OK;
+    hipError_t he = hipEventRecord(b->ev[0], origin);
+    for (int i = 1; i < n && he == hipSuccess; ++i)
+        if (b->hs[i]->stream != origin) he = hipStreamWaitEvent(b->hs[i]->stream, b->ev[0], 0);
+    for (int k = 0; k < b->graph_steps && rc == PF_LBM_OK && he == hipSuccess; ++k)
+        for (int i = 0; i < n && rc == PF_LBM_OK; ++i) rc = eager_step(b->hs[i]);
+    for (int i = 1; i < n && he == hipSuccess; ++i)
+        if (b->hs[i]->stream != origin) {
+            he = hipEventRecord(b->ev[i], b->hs[i]->stream);
+            if (he == hipSuccess) he = hipStreamWaitEvent(origin, b->ev[i], 0);
+        }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(origin, &g);
+    for (int i = 0; i < n; ++i) b->hs[i]->steps = s0[i];
+    if (rc != PF_LBM_OK || he != hipSuccess || e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, rc != PF_LBM_OK ? rc : PF_LBM_EDEVICE, "capture of the batch failed");
+    }
+    const hipError_t e2 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        b->graph = nullptr;
+        return bfail(b, PF_LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    }
+    for (int i = 0; i < n; ++i) b->parity[i] = (int)(b->hs[i]->steps & 1);
+    return PF_LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_lbm_batch_create(pf_lbm *const *handles, int32_t n, int32_t graph_steps, pf_lbm_batch **out) {
+    if (!handles || n < 1 || !out) return fail(nullptr, PF_LBM_EINVAL, "handles or out is NULL, or n < 1");
+    if (graph_steps < 2 || (graph_steps & 1)) return fail(nullptr, PF_LBM_EINVAL, "graph_steps must be even and >= 2");
+    for (int i = 0; i < n; ++i) {
+        if (!handles[i]) return fail(nullptr, PF_LBM_EINVAL, "handle %d is NULL", i);
+        if (!handles[i]->stream) return fail(nullptr, PF_LBM_EINVAL, "handle %d is bound to the default stream", i);
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == handles[i]) return fail(nullptr, PF_LBM_EINVAL, "handle %d repeats handle %d", i, j);
+    }
+    pf_lbm_batch *b = new (std::nothrow) pf_lbm_batch();
+    if (!b) return fail(nullptr, PF_LBM_ENOMEM, "host allocation failed");
+    b->hs.assign(handles, handles + n);
+    b->graph_steps = graph_steps;
+    b->parity.assign(n, -1);
+    b->ev.resize(n, nullptr);
+    for (int i = 0; i < n; ++i)
+        if (hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) {
+            pf_lbm_batch_destroy(b);
+            return fail(nullptr, PF_LBM_EDEVICE, "hipEventCreateWithFlags failed");
+        }
+    *out = b;
+    return PF_LBM_OK;
+}
+
+int pf_lbm_batch_step(pf_lbm_batch *b, int32_t n_steps) {
+    if (!b) return fail(nullptr, PF_LBM_EINVAL, "batch is NULL");
+    if (n_steps < 0) return bfail(b, PF_LBM_EINVAL, "n_steps must be >= 0");
+    const int n = (int)b->hs.size();
+    for (pf_lbm *h : b->hs)
+        if (h->timing) return bfail(b, PF_LBM_EINVAL, "a handle of the batch is timing");
+    hipStream_t origin = b->hs[0]->stream;
+    int left = n_steps;
+    while (left >= b->graph_steps) {
+        bool same = b->graph != nullptr;
+        for (int i = 0; i < n && same; ++i) same = b->parity[i] == (int)(b->hs[i]->steps & 1);
+        if (!same) {
+            const int rc = batch_capture(b);
+            if (rc != PF_LBM_OK) return rc;
+        }
+        // work queued on the instances' own streams precedes the replay, which precedes any
+        // later work on them
+        for (int i = 1; i < n; ++i)
+            if (b->hs[i]->stream != origin) {
+                BCHK(b, hipEventRecord(b->ev[i], b->hs[i]->stream));
+                BCHK(b, hipStreamWaitEvent(origin, b->ev[i], 0));
+            }
+        BCHK(b, hipGraphLaunch(b->graph, origin));
+        BCHK(b, hipEventRecord(b->ev[0], origin));
+        for (int i = 1; i < n; ++i)
+            if (b->hs[i]->stream != origin) BCHK(b, hipStreamWaitEvent(b->hs[i]->stream, b->ev[0], 0));
+        for (pf_lbm *h : b->hs) h->steps += b->graph_steps;
+        left -= b->graph_steps;
+    }
+    if (left > 0) {
+        pf_lbm *const *hs = b->hs.data();
+        const int rc = pf_lbm_step_batch(hs, n, left);
+        if (rc != PF_LBM_OK) return bfail(b, rc, "remainder steps failed");
+    }
+    return PF_LBM_OK;
+}
+
+void pf_lbm_batch_destroy(pf_lbm_batch *b) {
+    if (!b) return;
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete b;
+}
+
+const char *pf_lbm_batch_last_error(const pf_lbm_batch *b) { return b ? b->err.c_str() : g_init_error.c_str(); }
+
 int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3) {
     if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
     if (steps_per_candidate < 2) return fail(h, PF_LBM_EINVAL, "steps_per_candidate must be >= 2");

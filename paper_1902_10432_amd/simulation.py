@@ -156,3 +156,29 @@ def step_batch(sims, n_steps: int) -> None:
     if rc != B.PF_LBM_OK:
         errs = [B.pf_lbm_last_error(s._h) for s in sims]
         raise PfLbmError(rc, "; ".join(e for e in errs if e) or B.pf_lbm_last_error(None))
+
+
+class Batch:
+    """Independent simulations stepped as one captured HIP graph (pf_lbm_batch_*): graph_steps
+    steps of every instance per replay.  The simulations must stay alive while the batch is
+    used."""
+
+    def __init__(self, sims, graph_steps: int = 2):
+        self.sims = list(sims)
+        rc, h = B.pf_lbm_batch_create([s._h for s in self.sims], graph_steps)
+        if rc != B.PF_LBM_OK:
+            raise PfLbmError(rc, B.pf_lbm_last_error(None))
+        self._h = h
+
+    def step(self, n: int) -> None:
+        rc = B.pf_lbm_batch_step(self._h, n)
+        if rc != B.PF_LBM_OK:
+            raise PfLbmError(rc, B.pf_lbm_batch_last_error(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            B.pf_lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -56,6 +56,31 @@ def test_batch_matches_individual_runs(torch_cuda):
             assert np.array_equal(x, y)
 
 
+def test_batch_graph_matches_individual_runs(torch_cuda):
+    """All instances captured into one HIP graph (4 steps per replay) and replayed: per instance
+    the same bits as stepping it alone, also across an instance stepped on its own in between
+    (parity change forces a new capture) and a remainder that is not a whole replay."""
+    from paper_1902_10432_amd.simulation import Batch
+    ws = [bridge_pair(*args) for args in SMALL]
+    _print("case batch graph of " + ", ".join(str(w.shape) for w in ws))
+    alone = [_sim(w) for w in ws]
+    for s in alone:
+        s.step(31)
+    together = [_sim(w) for w in ws]
+    b = Batch(together, graph_steps=4)
+    b.step(12)
+    together[1].step(3)
+    b.step(8)
+    together[0].step(3)
+    together[2].step(3)
+    b.step(8)
+    for a, t in zip(alone, together):
+        assert t.diag()["step"] == 31
+        for x, y in zip(_state(a), _state(t)):
+            assert np.array_equal(x, y)
+    b.close()
+
+
 def test_force_history_matches_per_step_forces(torch_cuda):
     w = bridge_pair(*SMALL[0])
     s = _sim(w)
