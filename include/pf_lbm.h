@@ -224,6 +224,13 @@ int pf_lbm_autotune(pf_lbm *h, int32_t steps_per_candidate, double *out3);
  * not built for the precision and lattice), PF_LBM_EINVAL. */
 int pf_lbm_set_tile(pf_lbm *h, int32_t rows, int32_t planes);
 
+/* Entries of the per-step list of nodes that changed side (Sec. 3.2.2 node conversion) that the
+ * handle uses, in [0, 65536] (the default, the list's size in the workspace).  When a step's
+ * conversions exceed it, the conversion gather and the closing pass scan the whole bounding box of
+ * the phase fields instead of the list; the results are the same.  Lower values exist to run that
+ * path on purpose (tests).  Errors: PF_LBM_EINVAL (out of range or NULL handle). */
+int pf_lbm_set_event_capacity(pf_lbm *h, int32_t entries);
+
 /* Release the handle (the workspace stays the caller's).  NULL is ignored. */
 void pf_lbm_destroy(pf_lbm *h);
 

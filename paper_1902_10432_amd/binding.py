@@ -40,7 +40,7 @@ PF_LBM_DST_F64 = 0
 PF_LBM_DST_F32 = 1
 
 EXPORTED = ("pf_lbm_init", "pf_lbm_step", "pf_lbm_step_noalloc", "pf_lbm_forces", "pf_lbm_fields", "pf_lbm_diagnostics",
-            "pf_lbm_timing", "pf_lbm_force_history", "pf_lbm_step_batch", "pf_lbm_autotune", "pf_lbm_set_tile", "pf_lbm_destroy",
+            "pf_lbm_timing", "pf_lbm_force_history", "pf_lbm_step_batch", "pf_lbm_autotune", "pf_lbm_set_tile", "pf_lbm_set_event_capacity", "pf_lbm_destroy",
             "pf_lbm_last_error", "pf_lbm_batch_create", "pf_lbm_batch_step", "pf_lbm_batch_destroy",
             "pf_lbm_batch_last_error")
 
@@ -117,6 +117,8 @@ def load_library():
     lib.pf_lbm_batch_last_error.argtypes = [C.c_void_p]
     lib.pf_lbm_set_tile.restype = C.c_int
     lib.pf_lbm_set_tile.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    lib.pf_lbm_set_event_capacity.restype = C.c_int
+    lib.pf_lbm_set_event_capacity.argtypes = [C.c_void_p, C.c_int32]
     lib.pf_lbm_destroy.restype = None
     lib.pf_lbm_destroy.argtypes = [C.c_void_p]
     lib.pf_lbm_last_error.restype = C.c_char_p

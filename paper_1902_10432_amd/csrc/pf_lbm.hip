@@ -62,6 +62,12 @@ struct pf_lbm {
     // tile shape of the fluid pass, which leaves the arithmetic unchanged (pf_lbm_autotune): rows
     // of the 64-wide tile (block of 64 x fluid_ty threads) and planes per z-chunk
     int fluid_ty = 8, fluid_tz = 32;
+    // entries of the per-step event list in use (at most EV_CAP; fewer only to exercise the
+    // box-scan path that an overflowing list takes)
+    uint32_t ev_cap = EV_CAP;
+    // launch-shape generation: raised whenever captured graphs of the handle become stale, so a
+    // batch graph that holds its steps recaptures too
+    unsigned gen = 0;
     long long steps = 0;
     std::vector<double> sigma;
     std::string err;
@@ -316,15 +322,15 @@ void launch_phase_update(pf_lbm *h, const Prm<T> &p, int par, StepState *st, con
                          uint32_t *evlist) {
     dim3 g(h->box_grid), b(256);
     if (h->nb <= 1)
-        k_phase_update<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
+        k_phase_update<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
     else if (h->nb <= 2)
-        k_phase_update<T, 2><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
+        k_phase_update<T, 2><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
     else if (h->nb <= 4)
-        k_phase_update<T, 4><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
+        k_phase_update<T, 4><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
     else if (h->nb <= 8)
-        k_phase_update<T, 8><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
+        k_phase_update<T, 8><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
     else
-        k_phase_update<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, EV_CAP);
+        k_phase_update<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
 }
 
 // the three advection sweeps x (with the rigid-body update), y, z: a -> b -> a -> b
@@ -403,8 +409,8 @@ int enqueue_step(pf_lbm *h, double *parts = nullptr) {
         // conversion gather, then its closing pass: both usually return at once (no node changed
         // side), so a small grid
         const dim3 ge(std::min(h->box_grid, 64));
-        k_convert_gather<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, EV_CAP);
-        k_close_events<S, Lat><<<ge, b, 0, s>>>(p, par, st, fn, mask, nbw, psi, evlist, EV_CAP);
+        k_convert_gather<S, Lat><<<ge, b, 0, s>>>(p, par, st, mask, fn, psi, evlist, h->ev_cap);
+        k_close_events<S, Lat><<<ge, b, 0, s>>>(p, par, st, fn, mask, nbw, psi, evlist, h->ev_cap);
     }
     if (ev) HIPCHK(h, hipEventRecord(ev[3], s));
     HIPCHK(h, hipGetLastError());
@@ -683,6 +689,7 @@ void drop_graphs(pf_lbm *h) {
         g = nullptr;
     }
     h->graph_failed = false;
+    ++h->gen;
 }
 
 // capture GRAPH_STEPS[k] steps (an even number, starting at an even step) on the handle's
@@ -894,6 +901,7 @@ struct pf_lbm_batch {
     int graph_steps = 2;
     hipGraphExec_t graph = nullptr;
     std::vector<int> parity;              // step parity of each instance at capture
+    std::vector<unsigned> gen;            // launch-shape generation of each instance at capture
     std::vector<hipEvent_t> ev;           // one per instance (fork, join and ordering)
     std::string err;
 };
@@ -945,7 +953,10 @@ int batch_capture(pf_lbm_batch *b) {
         b->graph = nullptr;
         return bfail(b, PF_LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
     }
-    for (int i = 0; i < n; ++i) b->parity[i] = (int)(b->hs[i]->steps & 1);
+    for (int i = 0; i < n; ++i) {
+        b->parity[i] = (int)(b->hs[i]->steps & 1);
+        b->gen[i] = b->hs[i]->gen;
+    }
     return PF_LBM_OK;
 }
 
@@ -967,6 +978,7 @@ int pf_lbm_batch_create(pf_lbm *const *handles, int32_t n, int32_t graph_steps, 
     b->hs.assign(handles, handles + n);
     b->graph_steps = graph_steps;
     b->parity.assign(n, -1);
+    b->gen.assign(n, 0u);
     b->ev.resize(n, nullptr);
     for (int i = 0; i < n; ++i)
         if (hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) != hipSuccess) {
@@ -987,7 +999,8 @@ int pf_lbm_batch_step(pf_lbm_batch *b, int32_t n_steps) {
     int left = n_steps;
     while (left >= b->graph_steps) {
         bool same = b->graph != nullptr;
-        for (int i = 0; i < n && same; ++i) same = b->parity[i] == (int)(b->hs[i]->steps & 1);
+        for (int i = 0; i < n && same; ++i)
+            same = b->parity[i] == (int)(b->hs[i]->steps & 1) && b->gen[i] == b->hs[i]->gen;
         if (!same) {
             const int rc = batch_capture(b);
             if (rc != PF_LBM_OK) return rc;
@@ -1094,6 +1107,15 @@ int pf_lbm_set_tile(pf_lbm *h, int32_t rows, int32_t planes) {
     if (planes < 1 || planes > 4096) return fail(h, PF_LBM_EINVAL, "planes per chunk must lie in [1, 4096]");
     h->fluid_ty = rows;
     h->fluid_tz = planes;
+    drop_graphs(h);
+    return PF_LBM_OK;
+}
+
+int pf_lbm_set_event_capacity(pf_lbm *h, int32_t entries) {
+    if (!h) return fail(nullptr, PF_LBM_EINVAL, "handle is NULL");
+    if (entries < 0 || (uint32_t)entries > EV_CAP)
+        return fail(h, PF_LBM_EINVAL, "event capacity must lie in [0, %u]", EV_CAP);
+    h->ev_cap = (uint32_t)entries;
     drop_graphs(h);
     return PF_LBM_OK;
 }

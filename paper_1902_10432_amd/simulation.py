@@ -143,6 +143,11 @@ class Simulation:
         """Tile shape of the fluid pass: 64 x rows nodes, z-chunks of planes planes."""
         self._check(B.load_library().pf_lbm_set_tile(self._h, int(rows), int(planes)))
 
+    def set_event_capacity(self, entries: int) -> None:
+        """Entries of the per-step conversion event list in use; beyond them a step's conversion
+        passes scan the whole phase-field box (same results)."""
+        self._check(B.load_library().pf_lbm_set_event_capacity(self._h, int(entries)))
+
     def diag(self) -> dict:
         rc, out = B.pf_lbm_diagnostics(self._h)
         self._check(rc)

@@ -190,12 +190,13 @@ def two_spheres_bridge(n: int = 128, radius: float = 20.0, gap: float = 4.0, liq
 
 
 def bridge_pair(shape, r1: float, r2: float, gap: float, liquid_fraction: float, theta_deg: float,
-                width: float = 4.0, rho_v_init: float | None = None, **over) -> Workload:
+                width: float = 4.0, rho_v_init: float | None = None, fixed: bool = False, **over) -> Workload:
     """Two spheres of radii r1, r2 on the x axis with a surface gap, joined by a tanh-smoothed
     cylindrical bridge of liquid volume V_L = c V_S / (1 - c), c the liquid fraction
     V_L / (V_L + V_S) of Sec. 2.2 and V_S the two spheres' volume; the bridge radius is found by
     bisection (capped at the smaller radius).  rho_v_init, when given, replaces the flat-interface
-    vapour density as the initial vapour (BRIDGE_VAPOUR gives the reason)."""
+    vapour density as the initial vapour (BRIDGE_VAPOUR gives the reason).  fixed holds both
+    spheres in place (the rigid-body update leaves them at rest)."""
     nz, ny, nx = shape
     rv, rl = coexistence_densities()
     if rho_v_init is not None:
@@ -230,7 +231,7 @@ def bridge_pair(shape, r1: float, r2: float, gap: float, liquid_fraction: float,
     rperp = np.sqrt((y - cy) ** 2 + (z - cz) ** 2)
     rho = liquid_density(np.maximum(rperp - rb, np.abs(x - xm) - half), rl, rv, width)
     wet = wetting_rho_for_angle(theta_deg)
-    bodies = [_body(SPHERE_DENSITY, wet), _body(SPHERE_DENSITY, wet)]
+    bodies = [_body(SPHERE_DENSITY, wet, fixed=int(fixed)), _body(SPHERE_DENSITY, wet, fixed=int(fixed))]
     p = default_params(nx, ny, nz, 2, **over)
     meta = {"radii": (r1, r2), "gap": gap, "liquid_fraction": liquid_fraction, "theta_deg": theta_deg,
             "bridge_radius": rb, "liquid_volume": vol(rb), "target_volume": target, "centres": (c1, c2),

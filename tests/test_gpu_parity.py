@@ -106,6 +106,32 @@ def test_plates_bridge_fp32_200_steps(oracle_mod, torch_cuda):
     compare(sim, ref, 200, force_scale=math.pi * SIGMA * 6.0, lever=8.0, **FP32)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("cap", [0, 1])
+def test_event_list_overflow_path(oracle_mod, torch_cuda, precision, cap):
+    """The box-scan path that conversion takes when a step's event list overflows: with the list
+    cut to 0 or 1 entries (every step with conversions, or with more than one, overflows) the run
+    gives the same bits as with the full list, and in FP64 matches the oracle at round-off."""
+    from paper_1902_10432_amd.simulation import Simulation
+    w = tiny_moving_body(second_body=True)
+    w.params["e0"] = 0.5
+    _print(f"case event-list overflow cap={cap} {precision}")
+    full = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=precision)
+    cut = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=precision)
+    cut.set_event_capacity(cap)
+    full.step(60)
+    cut.step(60)
+    assert full.diag() == cut.diag() and cut.diag()["n_f2s"] > 1
+    assert np.array_equal(full.rho(), cut.rho()) and np.array_equal(full.phi(), cut.phi())
+    assert np.array_equal(full.mask(), cut.mask())
+    for k in ("F", "T", "X", "V", "W"):
+        assert np.array_equal(full.bodies()[k], cut.bodies()[k])
+    if precision == "fp64" and cap == 0:
+        ref = oracle_mod.Oracle(w.params, w.bodies, w.rho0, w.phi0)
+        ref.step(60)
+        compare(cut, ref, 60, lever=3.0, **FP64)
+
+
 def test_determinism_bitwise(torch_cuda):
     """Fixed-order reductions, no float atomics: two runs are bit-identical."""
     from paper_1902_10432_amd.simulation import Simulation
