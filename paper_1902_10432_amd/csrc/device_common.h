@@ -233,6 +233,104 @@ struct Prm {
     double threshold, mobility, eta, r_c, n_exp, e0, R_A;
     double phi_floor; // phase values at or below it count as absent (Sec. 3.3)
     double inv_n[3]; // 1 / nx, 1 / ny, 1 / nz
+    int tn[3];       // phase-field tiles per axis (ceil(n / tile edge))
+    int trad[3];     // tiles searched on each side for the activity of a tile (1, or 2 where the
+                     // last tile of the axis holds fewer than 3 nodes)
+};
+
+// Tiles of the phase-field work: 8 x 8 x 4 nodes in grid coordinates (the last tile of an axis
+// may be partial), one block of 256 threads per tile.  Each tile keeps a state word with two bits
+// per body a: bit 2a "some node of the tile has phi_a != 0", bit 2a + 1 "some node has
+// phi_a != 1" (all zero: 01, all one: 10, anything else: 11).  A body is active on a tile when
+// the tile or one of its neighbour tiles is mixed, or a neighbour's state differs from the
+// tile's, at the start of this step or of the previous one; elsewhere every stencil of the step
+// sees one constant (0 or 1) within 3 nodes, the update is the identity, and both phase buffers
+// already hold that constant, so the body's work is skipped there.  Pair-form masks: bit 2a.
+constexpr int TLX = 8, TLY = 8, TLZ = 4;
+constexpr uint32_t PAIR_LO = 0x55555555u;
+
+__host__ __device__ __forceinline__ uint32_t pair_mask(int nb) {
+    return nb >= 16 ? PAIR_LO : (PAIR_LO & ((1u << (2 * nb)) - 1u));
+}
+// bit a set where pair bit 2a is set
+__device__ __forceinline__ uint32_t pairs_to_bodies(uint32_t pm) {
+    uint32_t out = 0;
+    while (pm) {
+        const int b = __ffs(pm) - 1;
+        pm &= pm - 1;
+        out |= 1u << (b >> 1);
+    }
+    return out;
+}
+
+// the tiles that meet a box [lo, hi] (unwrapped coordinates, at most one period per axis):
+// per axis a run of cnt tiles starting at t0 (wrapped); tile k of the run and the nodes of a tile
+template <typename T>
+struct TileIter {
+    int lo[3], ext[3], n[3], t0[3], cnt[3], tn[3], total;
+    __device__ __forceinline__ TileIter(const int32_t *b, const Prm<T> &p) {
+        n[0] = p.nx;
+        n[1] = p.ny;
+        n[2] = p.nz;
+        const int te[3] = {TLX, TLY, TLZ};
+        total = 1;
+        for (int d = 0; d < 3; ++d) {
+            tn[d] = p.tn[d];
+            lo[d] = b[d];
+            ext[d] = b[3 + d] - b[d] + 1;
+            if (ext[d] <= 0) {
+                total = 0;
+                t0[d] = cnt[d] = 0;
+                continue;
+            }
+            int a = lo[d] % n[d];
+            a += a < 0 ? n[d] : 0;
+            const int e = a + ext[d] - 1;  // last cell, unwrapped from a
+            const int ta = a / te[d];
+            int c = e < n[d] ? e / te[d] - ta + 1 : (tn[d] - ta) + (e - n[d]) / te[d] + 1;
+            if (ext[d] >= n[d] || c >= tn[d]) {
+                t0[d] = 0;
+                c = tn[d];
+            } else {
+                t0[d] = ta;
+            }
+            cnt[d] = c;
+            total *= c;
+        }
+    }
+    // wrapped tile coordinates of run entry k and the tile's linear index
+    __device__ __forceinline__ int tile(int k, int *tc) const {
+        const int kx = k % cnt[0], r = k / cnt[0], ky = r % cnt[1], kz = r / cnt[1];
+        const int kk[3] = {kx, ky, kz};
+        for (int d = 0; d < 3; ++d) {
+            int t = t0[d] + kk[d];
+            tc[d] = t >= tn[d] ? t - tn[d] : t;
+        }
+        return tc[0] + tn[0] * (tc[1] + tn[1] * tc[2]);
+    }
+    // node j (0..255) of tile tc: wrapped (c) and unwrapped (u) coordinates; false when it lies
+    // outside the grid or the box
+    __device__ __forceinline__ bool node(const int *tc, int j, int *c, int *u) const {
+        const int l[3] = {j & 7, (j >> 3) & 7, j >> 6};
+        const int te[3] = {TLX, TLY, TLZ};
+        bool ok = true;
+        for (int d = 0; d < 3; ++d) {
+            c[d] = tc[d] * te[d] + l[d];
+            ok = ok && c[d] < n[d];
+            // (c - lo) mod n: the box's lo lies within one period below or above the grid
+            int m = c[d] - lo[d];
+            m += m < 0 ? n[d] : 0;
+            m += m < 0 ? n[d] : 0;
+            m -= m >= n[d] ? n[d] : 0;
+            u[d] = lo[d] + m;
+            ok = ok && m < ext[d];
+        }
+        return ok;
+    }
+    // does unwrapped coordinate v on axis d lie in the box
+    __device__ __forceinline__ bool inside(int d, int v) const {
+        return ext[d] >= n[d] || (v >= lo[d] && v < lo[d] + ext[d]);
+    }
 };
 
 // floor(k / d) for 0 <= k < 2^31, 0 < d, through a double reciprocal and one correction

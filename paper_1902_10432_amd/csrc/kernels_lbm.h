@@ -109,9 +109,13 @@ constexpr bool wall_in_fluid_pass() {
     return sizeof(S) == 2;
 }
 
-template <typename S, class L, typename PsiN>
-__device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, ArT<S> rin, PsiN psin, ArT<S> psi0,
-                                             S *__restrict__ fout, uint32_t solid_dirs, int x, int y, int z,
+// psin(I): psi of the neighbour in direction I; FP16 form: refn(I) its reference density R (the
+// encode of a population pushed there) and rown the node's own (the encode of its own slots),
+// both R(psi) of this step's psi, formed once per node with the window
+template <typename S, class L, typename PsiN, typename RefN>
+__device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, ArT<S> rin, PsiN psin, RefN refn,
+                                             ArT<S> psi0, ArT<S> rown, S *__restrict__ fout, uint32_t solid_dirs,
+                                             int x, int y, int z,
                                              long long Np, const cell_t *__restrict__ mask,
                                              const BodyDev *__restrict__ bodies) {
     using T = ArT<S>;
@@ -139,14 +143,9 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
 
     // pseudopotential force from pair differences of the neighbours' psi
     T s1x = T(0), s1y = T(0), s1z = T(0), s2x = T(0), s2y = T(0), s2z = T(0), s3x = T(0), s3y = T(0), s3z = T(0);
-    T rdst[L::Q];  // FP16 form: reference density of each push destination
     sfor<(L::Q - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1;
         const T pa = psin(std::integral_constant<int, i>{}), pb = psin(std::integral_constant<int, i + 1>{});
-        if constexpr (H) {
-            rdst[i] = ref_density(pa, p.rho0);
-            rdst[i + 1] = ref_density(pb, p.rho0);
-        }
         const T dp = pa - pb;
         if constexpr (Dir<i, L>::c2 == 1) {
             if constexpr (Dir<i, L>::x != 0) s1x += T(Dir<i, L>::x) * dp;
@@ -163,7 +162,6 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
         }
     });
     const T gp = -p.G * psi0;
-    const T rown = H ? ref_density(psi0, p.rho0) : T(0);  // reference of this node's own slots
     const T w1 = T(L::wshell[1]), w2 = T(L::wshell[2]);
     T Fx = w1 * s1x + w2 * s2x, Fy = w1 * s1y + w2 * s2y, Fz = w1 * s1z + w2 * s2z;
     if constexpr (L::Q == 27) {
@@ -206,7 +204,7 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
         sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0)
-                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
+                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * refn(I)));
         });
     } else if constexpr (!wall_in_fluid_pass<S>()) {
         // f*_i into slot opp(i); the force scan adds the moving-wall term and the mass correction
@@ -214,7 +212,7 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0) {
                 if (!(solid_dirs & (1u << i)))
-                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
+                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * refn(I)));
                 else
                     stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i], Dir<i, L>::template w<T>() * rown));
             }
@@ -227,7 +225,7 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0) {
                 if (!(solid_dirs & (1u << i))) {
-                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * rdst[i]));
+                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * refn(I)));
                 } else {
                     // the FP16 form's collision arithmetic is FP32: the lever arm about the body
                     // centre (minimum image, FP64) and the wall velocity at the link midpoint in FP32
@@ -253,11 +251,37 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
 // tile's populations of the plane being collided ([direction][node of the tile], stored form),
 // and, where the budget allows (DMA), the halo's populations, cell words and previous psi of
 // two planes, loaded straight into LDS.
+// entry of the psi window: psi, and in the FP16 form beside it the reference density R(psi) of the
+// node (formed once per node instead of once per population pushed to it)
+template <typename S>
+using WinE = std::conditional_t<sizeof(S) == 2, float2, ArT<S>>;
+template <typename S>
+__device__ __forceinline__ ArT<S> win_psi(const WinE<S> &e) {
+    if constexpr (sizeof(S) == 2)
+        return e.x;
+    else
+        return e;
+}
+template <typename S>
+__device__ __forceinline__ ArT<S> win_ref(const WinE<S> &e) {
+    if constexpr (sizeof(S) == 2)
+        return e.y;
+    else
+        return ArT<S>(0);
+}
+template <typename S>
+__device__ __forceinline__ WinE<S> win_entry(ArT<S> psi, ArT<S> rho0) {
+    if constexpr (sizeof(S) == 2)
+        return make_float2(psi, ref_density(psi, rho0));
+    else
+        return psi;
+}
+
 template <typename S, class L, int TY, bool DMA>
 struct FluidLds {
     // halo entries: the rows below and above the tile (64 each), the two columns (TY + 2 each)
     static constexpr int NH = DMA ? 128 + 2 * (TY + 2) : 1, NB = DMA ? 2 : 1;
-    ArT<S> ring[3][TY + 2][66];
+    WinE<S> ring[3][TY + 2][66];
     S pop[L::Q][64 * TY];
     S hpop[NB][L::Q][NH];
     cell_t hmask[NB][NH];
@@ -423,13 +447,14 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
             sfor<L::Q>([&](auto I) { hi.v[I] = ldb(fin + (long long)I * np, is); });
             hp = node_psi_of<S, L>(p, bodies, hi.m, hi.pp, [&](auto I) { return hi.v[decltype(I)::value]; });
         }
-        lds.ring[slot(zz)][hly + 1][hlx + 1] = hp;
+        lds.ring[slot(zz)][hly + 1][hlx + 1] = win_entry<S>(hp, p.rho0);
     };
     auto own_psi = [&](int zz, const NodeIn<S, L> (&o)[RPT]) {
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
-            lds.ring[slot(zz)][wv + W * r + 1][tx + 1] =
-                node_psi_of<S, L>(p, bodies, o[r].m, o[r].pp, [&](auto I) { return o[r].v[decltype(I)::value]; });
+            lds.ring[slot(zz)][wv + W * r + 1][tx + 1] = win_entry<S>(
+                node_psi_of<S, L>(p, bodies, o[r].m, o[r].pp, [&](auto I) { return o[r].v[decltype(I)::value]; }),
+                p.rho0);
     };
 
     NodeIn<S, L> A[RPT], B[RPT];
@@ -484,9 +509,9 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
             if (valid[r]) {
                 const uint32_t idx = own_xy[r] + zo;
                 // the node's entry in each window plane: neighbours are fixed offsets from it
-                const T *rm = &lds.ring[slot(z - 1)][ty + 1][tx + 1], *r0 = &lds.ring[slot(z)][ty + 1][tx + 1],
-                        *rp = &lds.ring[slot(z + 1)][ty + 1][tx + 1];
-                const T psi0 = *r0;
+                const WinE<S> *rm = &lds.ring[slot(z - 1)][ty + 1][tx + 1], *r0 = &lds.ring[slot(z)][ty + 1][tx + 1],
+                              *rp = &lds.ring[slot(z + 1)][ty + 1][tx + 1];
+                const T psi0 = win_psi<S>(*r0);
                 psi[idx] = psi0;
                 const cell_t w0 = cm[r];
                 if (!(w0 & C_SOLID)) {
@@ -498,14 +523,16 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
                     else
                         solid_dirs = nbw[idx];
                     const T rin = H ? ref_density(cpp[r], p.rho0) : T(0);  // reference of the inputs
+                    // the neighbour's window entry: fixed offsets from the node's
+                    auto nbr = [&](auto I) -> const WinE<S> & {
+                        constexpr int i = decltype(I)::value;
+                        constexpr int o = Dir<i, L>::y * 66 + Dir<i, L>::x;
+                        return Dir<i, L>::z < 0 ? rm[o] : (Dir<i, L>::z > 0 ? rp[o] : r0[o]);
+                    };
                     collide_push<S, L>(
-                        p, cur, rin,
-                        [&](auto I) {
-                            constexpr int i = decltype(I)::value;
-                            constexpr int o = Dir<i, L>::y * 66 + Dir<i, L>::x;
-                            return Dir<i, L>::z < 0 ? rm[o] : (Dir<i, L>::z > 0 ? rp[o] : r0[o]);
-                        },
-                        psi0, fout, solid_dirs, x, y0 + ty, z, plane_stride(), mask, bodies);
+                        p, cur, rin, [&](auto I) { return win_psi<S>(nbr(I)); },
+                        [&](auto I) { return win_ref<S>(nbr(I)); }, psi0, win_ref<S>(*r0), fout, solid_dirs, x,
+                        y0 + ty, z, plane_stride(), mask, bodies);
                 }
             }
             cm[r] = A[r].m;

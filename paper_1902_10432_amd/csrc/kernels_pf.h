@@ -41,92 +41,46 @@ __device__ __forceinline__ void block_totals(const double *part, int nblk, int K
 
 // One directional sweep (axis AX) of d phi_a/dt = -u_B . grad phi_a in conservative form for
 // every body a: phi_i -= F_{i+1/2} - F_{i-1/2}.  The rigid velocity component along the sweep
-// does not vary along the sweep line, so the update is exactly conservative.
-//
-// The first sweep (AX = 0) opens with the rigid-body update of Sec. 3.1.1: every block sums the
-// force partials of this step (momentum exchange, pseudopotential reaction, repulsion) in the
-// same fixed order and advances the bodies from the current table with dt = 1: V += F/M,
-// X += V, omega += I^-1 T; block 0 publishes the result (with F, T) in the next table, which the
-// later kernels of the step read.
-// hist (first sweep): ring of hcap steps of per-body force and torque, [step][body][6]
+// does not vary along the sweep line, so the update is exactly conservative.  The bodies' motion
+// is that of the rigid-body update of this step (the next table).  The sweep visits the tiles of
+// the box, one per block, and on each only the bodies active there (tact, pair form); elsewhere
+// its update is the identity.
 template <typename T, int AX, int NBMAX>
-__global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState *st, const BodyDev *__restrict__ cur,
-                                                BodyDev *__restrict__ next, const double *__restrict__ fpart, int fblk,
+__global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState *st, const BodyDev *__restrict__ next,
                                                 const double *__restrict__ src, double *__restrict__ dst,
-                                                double *__restrict__ hist, int hcap) {
-    __shared__ double tot[PF_LBM_MAX_BODIES * 6];
+                                                const uint32_t *__restrict__ tact) {
     __shared__ double lb[PF_LBM_MAX_BODIES][9];  // X, V, W of each body for this sweep
     const int tid = threadIdx.x;
     const int nbod = p.nb;
     // the box words are read first so that their latency overlaps the body-table reads
     int32_t box[6];
     for (int d = 0; d < 6; ++d) box[d] = st->box[parity][d];
-    if (AX == 0) {
-        block_totals(fpart, fblk, nbod * 6, tot);
-        if (tid < nbod) {
-            const BodyDev &B = cur[tid];
-            const double *F = &tot[tid * 6], *Tq = &tot[tid * 6 + 3];
-            double X[3], V[3], W[3];
-            for (int d = 0; d < 3; ++d) {
-                X[d] = B.X[d];
-                V[d] = B.V[d];
-                W[d] = B.W[d];
-            }
-            if ((p.flags & PF_LBM_MOTION) && !B.fixed) {
-                for (int d = 0; d < 3; ++d) V[d] += F[d] / B.M;
-                for (int d = 0; d < 3; ++d) X[d] += V[d];
-                for (int d = 0; d < 3; ++d)
-                    W[d] += B.Iinv[3 * d + 0] * Tq[0] + B.Iinv[3 * d + 1] * Tq[1] + B.Iinv[3 * d + 2] * Tq[2];
-            }
-            for (int d = 0; d < 3; ++d) {
-                lb[tid][d] = X[d];
-                lb[tid][3 + d] = V[d];
-                lb[tid][6 + d] = W[d];
-            }
-            if (blockIdx.x == 0) {
-                BodyDev Bn = B;
-                bool finite = true;
-                for (int d = 0; d < 3; ++d) {
-                    Bn.F[d] = F[d];
-                    Bn.T[d] = Tq[d];
-                    Bn.X[d] = X[d];
-                    Bn.V[d] = V[d];
-                    Bn.W[d] = W[d];
-                    finite = finite && isfinite(F[d]) && isfinite(Tq[d]) && isfinite(X[d]) && isfinite(V[d]) && isfinite(W[d]);
-                }
-                next[tid] = Bn;
-                if (!finite) atomicOr(&st->err, 1u);
-                if (hist) {
-                    double *hrow = hist + ((long long)((st->step_no - 1u) % (uint32_t)hcap) * nbod + tid) * 6;
-                    for (int d = 0; d < 3; ++d) {
-                        hrow[d] = F[d];
-                        hrow[3 + d] = Tq[d];
-                    }
-                }
-            }
+    if (tid < nbod)
+        for (int d = 0; d < 3; ++d) {
+            lb[tid][d] = next[tid].X[d];
+            lb[tid][3 + d] = next[tid].V[d];
+            lb[tid][6 + d] = next[tid].W[d];
         }
-    } else {
-        if (tid < nbod)
-            for (int d = 0; d < 3; ++d) {
-                lb[tid][d] = next[tid].X[d];
-                lb[tid][3 + d] = next[tid].V[d];
-                lb[tid][6 + d] = next[tid].W[d];
-            }
-    }
     __syncthreads();
-    const BoxIter it(box, p.nx, p.ny, p.nz);
+    const TileIter<T> ti(box, p);
     const int n[3] = {p.nx, p.ny, p.nz};
     const long long Np = p.Np;
     const int step = AX == 0 ? 1 : (AX == 1 ? p.nx : p.nx * p.ny);
     const int L = n[AX];
     constexpr int A1 = (AX + 1) % 3, A2 = (AX + 2) % 3;
+    const uint32_t pm = pair_mask(nbod);
     uint32_t cfl = 0;
     const int bid = xcd_block(blockIdx.x, gridDim.x);
-    for (int k = bid * 256 + tid; k < it.vol; k += gridDim.x * 256) {
+    for (int tk = bid; tk < ti.total; tk += gridDim.x) {
+        int tc[3];
+        const int tl = ti.tile(tk, tc);
+        uint32_t am = pairs_to_bodies(tact[tl] & pm);  // bodies active on the tile (uniform)
+        if (!am) continue;
         int u[3], c[3];
-        it.cell(k, u, c);
-        const int idx = c[0] + p.nx * (c[1] + p.ny * c[2]);
-        const int i = c[AX];
+        const bool ok = ti.node(tc, tid, c, u);
+        // threads off the grid or the box address node 0 and discard what they load
+        const int idx = ok ? c[0] + p.nx * (c[1] + p.ny * c[2]) : 0;
+        const int i = ok ? c[AX] : 0;
         // flat indices of the five cells i-2..i+2 along the axis (periodic); cells outside the
         // box hold no phase (the support stays 3 cells inside it through the step) and are not
         // read, so the intermediate buffers need no clearing outside the box
@@ -135,17 +89,23 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
 #pragma unroll
         for (int s = -2; s <= 2; ++s) {
             off[s + 2] = idx + (wrap2(i + s, L) - i) * step;
-            in[s + 2] = it.inside(AX, u[AX] + s);
+            in[s + 2] = ok && ti.inside(AX, u[AX] + s);
         }
-        // the stencils of up to four phases first, loaded unconditionally (the wrapped indices
-        // lie in the grid; values outside the box are masked), so that one memory latency covers
-        // the group
+        // the stencils of up to four active phases first, loaded unconditionally (the wrapped
+        // indices lie in the grid; values outside the box are masked), so that one memory latency
+        // covers the group
         constexpr int G = NBMAX < 4 ? NBMAX : 4;
-        for (int a0 = 0; a0 < nbod; a0 += G) {
+        while (am) {
+            int ag[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                ag[g] = am ? __ffs(am) - 1 : -1;
+                am &= am ? am - 1u : 0u;
+            }
             double sv[G][5];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const double *s0 = src + (long long)(a0 + g < nbod ? a0 + g : a0) * Np;
+                const double *s0 = src + (long long)(ag[g] >= 0 ? ag[g] : ag[0]) * Np;
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
                     const double t = s0[off[q]];
@@ -154,8 +114,9 @@ __global__ __launch_bounds__(256) void k_advect(Prm<T> p, int parity, StepState 
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const int a = a0 + g;
-                if (a >= nbod) break;
+                const int a = ag[g];
+                if (a < 0) break;
+                if (!ok) continue;
                 // velocity component along AX at this sweep line
                 const double r1 = mimg_r((double)c[A1] - lb[a][A1], n[A1], p.inv_n[A1]);
                 const double r2 = mimg_r((double)c[A2] - lb[a][A2], n[A2], p.inv_n[A2]);
@@ -406,16 +367,21 @@ __device__ __forceinline__ void append_events(StepState *st, uint32_t *evlist, u
     }
 }
 
-// Phase update after the advection sweeps, one box node per thread: kinetics (kinetics_node;
-// without kinetics the phases pass unchanged), reclassification with the event list, per-block
-// partials.  Face neighbours outside the box hold no phase and are not read.
+// Phase update after the advection sweeps, one tile of the box per block and one node per thread,
+// on the tiles where some body is active: kinetics (kinetics_node; without kinetics the phases
+// pass unchanged), reclassification with the event list, per-block partials, and the tile's new
+// state word.  Bodies inactive on the tile hold their tile constant at every node the stencil
+// reaches, so their values are taken from the state word instead of memory.  On a tile where
+// no body is active nothing changes; the bodies that fill it (phi = 1) add its node count to
+// their volume sums.  Face neighbours outside the box hold no phase and are not read.
 template <typename PT, int NBMAX>
 __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, StepState *st,
                                                       const BodyDev *__restrict__ bodies,
                                                       const double *__restrict__ sigma, const double *__restrict__ src,
                                                       double *__restrict__ dst, cell_t *__restrict__ mask,
                                                       ClassifyPart *__restrict__ cpart, uint32_t *__restrict__ evlist,
-                                                      uint32_t evcap) {
+                                                      uint32_t evcap, const uint32_t *__restrict__ tact,
+                                                      uint4 *__restrict__ tstate) {
     constexpr int NP = NBMAX + 1;
     __shared__ double sg[NP * NP];
     __shared__ double hh[NP];
@@ -430,48 +396,219 @@ __global__ __launch_bounds__(256) void k_phase_update(Prm<PT> p, int parity, Ste
     }
     if (tid < NP) hh[tid] = (tid == 0 || tid > nbod) ? 0.0 : bodies[tid - 1].h;
     __syncthreads();
-    const BoxIter it(box, p.nx, p.ny, p.nz);
+    const TileIter<PT> ti(box, p);
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const long long Np = p.Np;
     const bool kin = (p.flags & PF_LBM_KINETICS) != 0;
     const double PI = 3.14159265358979323846;
     const double mu = PI * PI / (p.eta * p.eta), vterm = PI * PI / (4.0 * p.eta), M = p.mobility;
+    const uint32_t pm = pair_mask(nbod);
+    const int wave = tid >> 6, lane = tid & 63;
     ClassAcc<NBMAX> acc;
     const int bid = xcd_block(blockIdx.x, gridDim.x);
-    for (int base = bid * 256; base < it.vol; base += gridDim.x * 256) {
-        const int k = base + tid;
-        uint32_t event = 0;
-        if (k < it.vol) {
-            int u[3], c[3];
-            it.cell(k, u, c);
+    for (int tk = bid; tk < ti.total; tk += gridDim.x) {
+        int tc[3];
+        const int tl = ti.tile(tk, tc);
+        const uint32_t act = tact[tl] & pm;  // uniform
+        const uint4 sw = tstate[tl];
+        const uint32_t s0 = (sw.x | sw.y) | (sw.z | sw.w);
+        if (!act) {
+            if (tid == 0) {
+                const int cnt = min(TLX, nx - tc[0] * TLX) * min(TLY, ny - tc[1] * TLY) * min(TLZ, nz - tc[2] * TLZ);
+#pragma unroll
+                for (int a = 0; a < NBMAX; ++a)
+                    if (a < nbod && ((s0 >> (2 * a)) & 3u) == 1u) acc.vol[a] += (double)cnt;
+            }
+            continue;
+        }
+        uint32_t event = 0, bits = 0;
+        int u[3], c[3];
+        const bool ok = ti.node(tc, tid, c, u);
+        if (ok) {
             const int idx = c[0] + nx * (c[1] + ny * c[2]);
             const cell_t old = mask[idx];  // issued with the phase loads
-            double v[NBMAX], out[NBMAX];
+            double v[NBMAX], out[NBMAX], cst[NBMAX];
+            bool on[NBMAX];
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a) {
-                v[a] = a < nbod ? src[(long long)a * Np + idx] : 0.0;
+                on[a] = a < nbod && ((act >> (2 * a)) & 1u);
+                cst[a] = (a < nbod && ((s0 >> (2 * a)) & 3u) == 1u) ? 1.0 : 0.0;
+                v[a] = on[a] ? src[(long long)a * Np + idx] : cst[a];
                 out[a] = v[a];
             }
             if (kin) {
                 const Nbr nb(c[0], c[1], c[2], nx, ny, nz);
                 const int offs[6] = {nb.xp, nb.xm, nb.yp, nb.ym, nb.zp, nb.zm};
-                const bool ins[6] = {it.inside(0, u[0] + 1), it.inside(0, u[0] - 1), it.inside(1, u[1] + 1),
-                                     it.inside(1, u[1] - 1), it.inside(2, u[2] + 1), it.inside(2, u[2] - 1)};
+                const bool ins[6] = {ti.inside(0, u[0] + 1), ti.inside(0, u[0] - 1), ti.inside(1, u[1] + 1),
+                                     ti.inside(1, u[1] - 1), ti.inside(2, u[2] + 1), ti.inside(2, u[2] - 1)};
                 kinetics_node<NBMAX>(
                     v,
                     [&](int e, int a) {
-                        return (a < nbod && ins[e]) ? src[(long long)a * Np + idx + offs[e]] : 0.0;
+                        return on[a] ? (ins[e] ? src[(long long)a * Np + idx + offs[e]] : 0.0) : cst[a];
                     },
                     nbod, sg, hh, mu, vterm, M, p.phi_floor, out);
             }
+            // every body is written: a body inactive here keeps its constant, except where the
+            // final rescale of the solids moves it by rounding (its state word then shows it)
 #pragma unroll
             for (int a = 0; a < NBMAX; ++a)
-                if (a < nbod) dst[(long long)a * Np + idx] = out[a];
+                if (a < nbod) {
+                    dst[(long long)a * Np + idx] = out[a];
+                    bits |= (out[a] != 0.0 ? 1u : 0u) << (2 * a);
+                    bits |= (out[a] != 1.0 ? 2u : 0u) << (2 * a);
+                }
             event = acc.node(p, bodies, mask, idx, u, c, out, old);
+        } else if (c[0] < nx && c[1] < ny && c[2] < nz) {
+            bits = pm << 1;  // a node of the tile outside the box: every phase is 0 there
         }
         append_events(st, evlist, evcap, event);
+        // the state word of this wave's layer of the tile from the new phases
+        bits = wave_or(bits);
+        if (lane == 0) ((uint32_t *)tstate)[4 * tl + wave] = bits;
+        // one tile's loads at a time: letting the next tile's loads move up doubles the registers
+        asm volatile("" ::: "memory");
     }
     acc.finish(nbod, st, cpart);
+}
+
+// The rigid-body update of Sec. 3.1.1 (one block): the force partials of this step (momentum
+// exchange, pseudopotential reaction, repulsion) summed in a fixed order, and the bodies advanced
+// from the current table with dt = 1: V += F/M, X += V, omega += I^-1 T, published with F and T in
+// the next table, which the later kernels of the step read.  hist: ring of hcap steps of per-body
+// force and torque, [step][body][6].
+__device__ __forceinline__ void rigid_body_update(int flags, int nbod, StepState *st, const BodyDev *__restrict__ cur,
+                                                  BodyDev *__restrict__ next, const double *__restrict__ fpart,
+                                                  int fblk, double *__restrict__ hist, int hcap) {
+    __shared__ double tot[PF_LBM_MAX_BODIES * 6];
+    const int tid = threadIdx.x;
+    block_totals(fpart, fblk, nbod * 6, tot);
+    if (tid < nbod) {
+        const BodyDev &B = cur[tid];
+        const double *F = &tot[tid * 6], *Tq = &tot[tid * 6 + 3];
+        BodyDev Bn = B;
+        bool finite = true;
+        const bool move = (flags & PF_LBM_MOTION) && !B.fixed;
+        for (int d = 0; d < 3; ++d) Bn.V[d] = move ? B.V[d] + F[d] / B.M : B.V[d];
+        for (int d = 0; d < 3; ++d) Bn.X[d] = move ? B.X[d] + Bn.V[d] : B.X[d];
+        for (int d = 0; d < 3; ++d)
+            Bn.W[d] = move ? B.W[d] + (B.Iinv[3 * d + 0] * Tq[0] + B.Iinv[3 * d + 1] * Tq[1] + B.Iinv[3 * d + 2] * Tq[2])
+                           : B.W[d];
+        for (int d = 0; d < 3; ++d) {
+            Bn.F[d] = F[d];
+            Bn.T[d] = Tq[d];
+            finite = finite && isfinite(F[d]) && isfinite(Tq[d]) && isfinite(Bn.X[d]) && isfinite(Bn.V[d]) &&
+                     isfinite(Bn.W[d]);
+        }
+        next[tid] = Bn;
+        if (!finite) atomicOr(&st->err, 1u);
+        if (hist) {
+            double *hrow = hist + ((long long)((st->step_no - 1u) % (uint32_t)hcap) * nbod + tid) * 6;
+            for (int d = 0; d < 3; ++d) {
+                hrow[d] = F[d];
+                hrow[3 + d] = Tq[d];
+            }
+        }
+    }
+}
+
+// After the force scan: the last block runs the rigid-body update; the others the activity of
+// the tiles of this step's box (one thread per tile, see TileIter): hot where the tile or a tile
+// within p.trad tiles is mixed or differs from it (thot[parity]); active where hot now or at the
+// previous step (tact).  States of tiles outside the box are those of their last visit (zero
+// phases unless the support was there), which can only add activity.  tstate: four words per
+// tile (one per z-layer of it), ORed.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_activity(Prm<T> p, int parity, StepState *st,
+                                                       const uint4 *__restrict__ tstate, uint32_t *__restrict__ thot,
+                                                       uint32_t *__restrict__ tact, const BodyDev *__restrict__ cur,
+                                                       BodyDev *__restrict__ next, const double *__restrict__ fpart,
+                                                       int fblk, double *__restrict__ hist, int hcap) {
+    if (blockIdx.x == gridDim.x - 1) {
+        rigid_body_update(p.flags, p.nb, st, cur, next, fpart, fblk, hist, hcap);
+        return;
+    }
+    const int nblk = gridDim.x - 1;
+    auto word = [&](int t) {
+        const uint4 w = tstate[t];
+        return (w.x | w.y) | (w.z | w.w);
+    };
+    const TileIter<T> ti(st->box[parity], p);
+    const uint32_t pm = pair_mask(p.nb);
+    const int ntl = p.tn[0] * p.tn[1] * p.tn[2];
+    // neighbour tile coordinate t + d (|d| <= 2) wrapped into [0, n) (n may be 1 or 2)
+    auto wrapt = [](int t, int n) {
+        t += t < 0 ? n : 0;
+        t += t < 0 ? n : 0;
+        t -= t >= n ? n : 0;
+        t -= t >= n ? n : 0;
+        return t;
+    };
+    const bool near = p.trad[0] == 1 && p.trad[1] == 1 && p.trad[2] == 1;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < ti.total; k += nblk * 256) {
+        int tc[3];
+        const int tl = ti.tile(k, tc);
+        uint32_t dif = 0;
+        if (near) {
+            // the 27 words in one round of loads
+            int xs[3], ys[3], zs[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                xs[d] = wrapt(tc[0] + d - 1, p.tn[0]);
+                ys[d] = p.tn[0] * wrapt(tc[1] + d - 1, p.tn[1]);
+                zs[d] = p.tn[0] * p.tn[1] * wrapt(tc[2] + d - 1, p.tn[2]);
+            }
+            uint32_t w[27];
+#pragma unroll
+            for (int j = 0; j < 27; ++j) w[j] = word(xs[j % 3] + ys[(j / 3) % 3] + zs[j / 9]);
+            const uint32_t s0 = w[13];
+#pragma unroll
+            for (int j = 0; j < 27; ++j) dif |= (w[j] ^ s0) | (w[j] & (w[j] >> 1) & PAIR_LO);
+        } else {
+            const uint32_t s0 = word(tl);
+            for (int dz = -p.trad[2]; dz <= p.trad[2]; ++dz) {
+                const int z = wrapt(tc[2] + dz, p.tn[2]);
+                for (int dy = -p.trad[1]; dy <= p.trad[1]; ++dy) {
+                    const int y = wrapt(tc[1] + dy, p.tn[1]);
+                    for (int dx = -p.trad[0]; dx <= p.trad[0]; ++dx) {
+                        const uint32_t s = word(wrapt(tc[0] + dx, p.tn[0]) + p.tn[0] * (y + p.tn[1] * z));
+                        dif |= (s ^ s0) | (s & (s >> 1) & PAIR_LO);
+                    }
+                }
+            }
+        }
+        const uint32_t hot = (dif | (dif >> 1)) & pm;
+        thot[(long long)parity * ntl + tl] = hot;
+        tact[tl] = hot | (thot[(long long)(parity ^ 1) * ntl + tl] & pm);
+    }
+}
+
+// State words of every tile from the phase fields (initialisation), and both steps' hot masks set
+// (every body active on every tile of the first two steps' boxes).  One tile per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_init(Prm<T> p, const double *__restrict__ phi, uint32_t *__restrict__ tstate,
+                                                   uint32_t *__restrict__ thot) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ntl = p.tn[0] * p.tn[1] * p.tn[2];
+    const uint32_t pm = pair_mask(p.nb);
+    for (int tl = blockIdx.x; tl < ntl; tl += gridDim.x) {
+        const int tc[3] = {tl % p.tn[0], (tl / p.tn[0]) % p.tn[1], tl / (p.tn[0] * p.tn[1])};
+        const int c[3] = {tc[0] * TLX + (tid & 7), tc[1] * TLY + ((tid >> 3) & 7), tc[2] * TLZ + (tid >> 6)};
+        uint32_t bits = 0;
+        if (c[0] < p.nx && c[1] < p.ny && c[2] < p.nz) {
+            const long long idx = c[0] + (long long)p.nx * (c[1] + (long long)p.ny * c[2]);
+            for (int a = 0; a < p.nb; ++a) {
+                const double v = phi[(long long)a * p.Np + idx];
+                bits |= (v != 0.0 ? 1u : 0u) << (2 * a);
+                bits |= (v != 1.0 ? 2u : 0u) << (2 * a);
+            }
+        }
+        bits = wave_or(bits);
+        if (lane == 0) tstate[4 * tl + wave] = bits;
+        if (tid == 0) {
+            thot[tl] = pm;
+            thot[ntl + tl] = pm;
+        }
+    }
 }
 
 // Classification of the initial phase fields (Sec. 3.2.2): solid iff the fluid fraction

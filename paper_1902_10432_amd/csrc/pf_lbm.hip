@@ -37,7 +37,8 @@ constexpr size_t STATIC_PARTS = (size_t)FORCE_GRID_MAX * PF_LBM_MAX_BODIES * 6;
 constexpr int MAX_DEVICES = 64;
 
 struct Layout {
-    size_t fA, fB, psi, psiB, phiA, phiB, mask, nbw, bodies, state, sigma, pforce, cpart, evlist, hist, total;
+    size_t fA, fB, psi, psiB, phiA, phiB, mask, nbw, bodies, state, sigma, pforce, cpart, evlist, hist, tstate, thot,
+        tact, total;
 };
 
 }  // namespace
@@ -107,7 +108,7 @@ int fail(pf_lbm *h, int code, const char *fmt, ...) {
 size_t pop_size(int prec) { return prec == PF_LBM_FP64 ? 8 : (prec == PF_LBM_FP16_STORE ? 2 : 4); }
 size_t real_size(int prec) { return prec == PF_LBM_FP64 ? 8 : 4; }
 
-Layout make_layout(long long Np, int nb, int prec, int q, int cpart_n, int force_grid) {
+Layout make_layout(long long Np, int nb, int prec, int q, int cpart_n, int force_grid, long long ntiles) {
     const size_t rs = real_size(prec), ps = pop_size(prec);
     Layout L{};
     size_t off = 0;
@@ -135,6 +136,10 @@ Layout make_layout(long long Np, int nb, int prec, int q, int cpart_n, int force
     L.cpart = take(sizeof(ClassifyPart) * cpart_n);
     L.evlist = take(sizeof(uint32_t) * EV_CAP);
     L.hist = take(sizeof(double) * HIST_CAP * std::max(nb, 1) * 6);
+    // phase-field tiles: state word, hot masks of this and the previous step, active masks
+    L.tstate = take(sizeof(uint32_t) * 4 * ntiles);  // one word per z-layer of the tile
+    L.thot = take(sizeof(uint32_t) * 2 * ntiles);
+    L.tact = take(sizeof(uint32_t) * ntiles);
     L.total = off;
     return L;
 }
@@ -266,6 +271,13 @@ Prm<T> make_prm(const pf_lbm *h) {
     p.inv_n[0] = 1.0 / h->cfg.nx;
     p.inv_n[1] = 1.0 / h->cfg.ny;
     p.inv_n[2] = 1.0 / h->cfg.nz;
+    const int n[3] = {h->cfg.nx, h->cfg.ny, h->cfg.nz}, te[3] = {TLX, TLY, TLZ};
+    for (int d = 0; d < 3; ++d) {
+        p.tn[d] = (n[d] + te[d] - 1) / te[d];
+        // a last tile of fewer than 3 nodes lets a 3-node reach skip a whole tile
+        const int last = n[d] - (p.tn[d] - 1) * te[d];
+        p.trad[d] = (p.tn[d] >= 3 && last < 3) ? 2 : 1;
+    }
     return p;
 }
 
@@ -319,45 +331,49 @@ T *fbuf(pf_lbm *h, int which) {
 template <typename T>
 void launch_phase_update(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *bodies,
                          const double *sigma, const double *src, double *dst, cell_t *mask, ClassifyPart *cpart,
-                         uint32_t *evlist) {
-    dim3 g(h->box_grid), b(256);
+                         uint32_t *evlist, const uint32_t *tact, uint4 *tstate) {
+    dim3 g(h->cgrid), b(256);
     if (h->nb <= 1)
-        k_phase_update<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
+        k_phase_update<T, 1><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap,
+                                                      tact, tstate);
     else if (h->nb <= 2)
-        k_phase_update<T, 2><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
+        k_phase_update<T, 2><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap,
+                                                      tact, tstate);
     else if (h->nb <= 4)
-        k_phase_update<T, 4><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
+        k_phase_update<T, 4><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap,
+                                                      tact, tstate);
     else if (h->nb <= 8)
-        k_phase_update<T, 8><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
+        k_phase_update<T, 8><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap,
+                                                      tact, tstate);
     else
-        k_phase_update<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap);
+        k_phase_update<T, 16><<<g, b, 0, h->stream>>>(p, par, st, bodies, sigma, src, dst, mask, cpart, evlist, h->ev_cap,
+                                                      tact, tstate);
 }
 
 // the three advection sweeps x (with the rigid-body update), y, z: a -> b -> a -> b
 template <typename T, int NBMAX>
-void launch_advect_n(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *cur, BodyDev *next,
-                     const double *pforce, int fbk, double *a, double *b) {
+void launch_advect_n(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *next, double *a, double *b,
+                     const uint32_t *tact) {
     const dim3 g(h->box_grid), bl(256);
     hipStream_t s = h->stream;
-    k_advect<T, 0, NBMAX><<<g, bl, 0, s>>>(p, par, st, cur, next, pforce, fbk, a, b, (double *)(h->ws + h->L.hist),
-                                           HIST_CAP);
-    k_advect<T, 1, NBMAX><<<g, bl, 0, s>>>(p, par, st, cur, next, nullptr, 0, b, a, nullptr, 0);
-    k_advect<T, 2, NBMAX><<<g, bl, 0, s>>>(p, par, st, cur, next, nullptr, 0, a, b, nullptr, 0);
+    k_advect<T, 0, NBMAX><<<g, bl, 0, s>>>(p, par, st, next, a, b, tact);
+    k_advect<T, 1, NBMAX><<<g, bl, 0, s>>>(p, par, st, next, b, a, tact);
+    k_advect<T, 2, NBMAX><<<g, bl, 0, s>>>(p, par, st, next, a, b, tact);
 }
 
 template <typename T>
-void launch_advect(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *cur, BodyDev *next,
-                   const double *pforce, int fbk, double *a, double *b) {
+void launch_advect(pf_lbm *h, const Prm<T> &p, int par, StepState *st, const BodyDev *next, double *a, double *b,
+                   const uint32_t *tact) {
     if (h->nb <= 1)
-        launch_advect_n<T, 1>(h, p, par, st, cur, next, pforce, fbk, a, b);
+        launch_advect_n<T, 1>(h, p, par, st, next, a, b, tact);
     else if (h->nb <= 2)
-        launch_advect_n<T, 2>(h, p, par, st, cur, next, pforce, fbk, a, b);
+        launch_advect_n<T, 2>(h, p, par, st, next, a, b, tact);
     else if (h->nb <= 4)
-        launch_advect_n<T, 4>(h, p, par, st, cur, next, pforce, fbk, a, b);
+        launch_advect_n<T, 4>(h, p, par, st, next, a, b, tact);
     else if (h->nb <= 8)
-        launch_advect_n<T, 8>(h, p, par, st, cur, next, pforce, fbk, a, b);
+        launch_advect_n<T, 8>(h, p, par, st, next, a, b, tact);
     else
-        launch_advect_n<T, 16>(h, p, par, st, cur, next, pforce, fbk, a, b);
+        launch_advect_n<T, 16>(h, p, par, st, next, a, b, tact);
 }
 
 // one time step (Sec. 3): fluid, body forces + rigid update, phase fields, reclassification
@@ -401,11 +417,16 @@ int enqueue_step(pf_lbm *h, double *parts = nullptr) {
     if (ev) HIPCHK(h, hipEventRecord(ev[2], s));
     if (h->nb > 0) {
         const int fbk = h->force_grid;
+        uint4 *tstate = (uint4 *)(h->ws + h->L.tstate);
+        uint32_t *thot = (uint32_t *)(h->ws + h->L.thot), *tact = (uint32_t *)(h->ws + h->L.tact);
         k_body_forces<S, Lat><<<dim3(fbk), dim3(64 * force_waves<T, Lat>()), 0, s>>>(p, par, st, fc, fn, psi, psi_prev,
                                                                                       mask, cur, pforce, nbw);
+        // tile activity, and in its last block the rigid-body update from the force partials
+        k_tile_activity<T><<<dim3(std::min(h->box_grid, 64) + 1), b, 0, s>>>(
+            p, par, st, tstate, thot, tact, cur, next, pforce, fbk, (double *)(h->ws + h->L.hist), HIST_CAP);
         // one kernel per sweep; the phase fields end in buffer A every step
-        launch_advect<T>(h, p, par, st, cur, next, pforce, fbk, phiA, phiB);
-        launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist);
+        launch_advect<T>(h, p, par, st, next, phiA, phiB, tact);
+        launch_phase_update<T>(h, p, par, st, next, sigma, phiB, phiA, mask, cpart, evlist, tact, tstate);
         // conversion gather, then its closing pass: both usually return at once (no node changed
         // side), so a small grid
         const dim3 ge(std::min(h->box_grid, 64));
@@ -453,6 +474,8 @@ int init_device(pf_lbm *h, const pf_lbm_body *bodies_in, const double *rho0, con
         ClassifyPart *cpart = (ClassifyPart *)(h->ws + h->L.cpart);
         k_classify_init<T><<<dim3(h->cgrid), b, 0, s>>>(p, 0, st, (const BodyDev *)(h->ws + h->L.bodies), phiA,
                                                              mask, cpart);
+        k_tile_init<T><<<dim3(std::max(1, std::min(gd, 4096))), b, 0, s>>>(p, phiA, (uint32_t *)(h->ws + h->L.tstate),
+                                                                           (uint32_t *)(h->ws + h->L.thot));
     }
     HIPCHK(h, hipMemcpyAsync(tmp, rho0, sizeof(double) * h->N, hipMemcpyHostToDevice, s));
     S *fA = fbuf<S>(h, 0), *fB = fbuf<S>(h, 1);
@@ -558,14 +581,18 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     // box kernels: about one thread per cell of the initial box with room to grow (grid-stride
     // loops cover larger boxes), at most 4096 blocks
     const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
-    // box kernels: grid-stride over the box with two blocks per CU of the 256, four for boxes
-    // above 2^20 cells (measured: on the 128^3 workload, 0.3 M cells, 512 blocks beat 256 and
-    // 1024, the launch and drain of more blocks costing more than their extra parallelism gains;
-    // on the 256^3 four-sphere workload 1024 beat 512 by 2 %)
-    const int box_grid = std::min(box_blocks, vol0 > (1LL << 20) ? 1024 : 512);
+    // box kernels: one tile of 256 nodes per block, about one block per tile of the initial box
+    // with room to grow (larger boxes are covered by grid-stride loops): each tile's work is a
+    // short chain of dependent loads, which many resident blocks overlap
+    const int box_grid = box_blocks;
     const int force_grid = std::min((box_blocks + 3) / 4, FORCE_GRID_MAX);
-    const int cgrid = box_grid;
-    const Layout L = make_layout(Np, n_bodies, cfg->precision, cfg->lattice, std::max(cgrid, box_grid), force_grid);
+    // phase update (and the classification partials it leaves): grid-stride over the tiles with
+    // two blocks per CU, four for boxes above 2^20 cells; more blocks were measured slower (each
+    // block's partials are summed at the start of the next step)
+    const int cgrid = std::min(box_blocks, vol0 > (1LL << 20) ? 1024 : 512);
+    const long long ntiles = (long long)((cfg->nx + TLX - 1) / TLX) * ((cfg->ny + TLY - 1) / TLY) * ((cfg->nz + TLZ - 1) / TLZ);
+    const Layout L = make_layout(Np, n_bodies, cfg->precision, cfg->lattice, std::max(cgrid, box_grid), force_grid,
+                                 ntiles);
     if (ws_bytes_needed) *ws_bytes_needed = L.total;
     if (!workspace) return PF_LBM_OK;
     if (!out) return fail(nullptr, PF_LBM_EINVAL, "out is NULL");
