@@ -5,7 +5,8 @@ Default workload: four spheres (R = 24) at the vertices of a regular tetrahedron
 liquid drop of 5 % liquid fraction, seeded 1e-3 perturbations of the phase fields, 30 degree
 wetting, 256^3 D3Q19, tau = 1.1, FP32 populations, rigid-body motion and phase-field kinetics on;
 beside it the same workload with FP16 population storage.  A step is the whole coupled step
-(every kernel).  Inputs are resident in HBM before the timed region.
+(every kernel).  Inputs are resident in HBM before the timed region.  The fluid pass runs its
+default tile of the precision (DEFAULT_TILES; --tile or --autotune choose another).
 
 Prints one JSON line: MLUPS (all nodes x steps / s), the step's algorithmic fraction of HBM peak,
 the dominant kernel's roofline (algorithmic bytes per launch over its mean launch time measured
@@ -59,18 +60,22 @@ def _bit_bytes(q: int) -> int:
 
 
 def step_bytes_per_cell(pop: int, arith: int, q: int = 19) -> float:
-    """Algorithmic bytes of one coupled step per node: q populations read and written, the
-    pseudopotential written once and read once, the cell word (and on D3Q27 the neighbour-bit
-    word) read once (the phase-field work on the box around the bodies is not counted)."""
-    return 2 * q * pop + 2 * arith + MASK_BYTES + _bit_bytes(q)
+    """Algorithmic bytes of one coupled step per node: q populations read and written, the cell
+    word (and on D3Q27 the neighbour-bit word) read, the pseudopotential written (the force scan
+    and the next step read it back at interface nodes only), and in the FP16-storage form the
+    previous step's pseudopotential read (the reference density of the stored deviations).  The
+    phase-field work on the tiles around the bodies is not counted."""
+    return 2 * q * pop + arith + MASK_BYTES + _bit_bytes(q) + (arith if pop == 2 else 0)
 
 
 def kernel_bytes(n_fluid: int, n_solid: int, pop: int, arith: int, q: int = 19) -> float:
-    """Algorithmic bytes of one collide-stream launch: a fluid node reads and writes its q
-    populations and reads its own pseudopotential and cell word (and on D3Q27 its neighbour-bit
-    word; neighbour values are re-reads of the same arrays); a solid node reads its cell word
-    only."""
-    return n_fluid * (2 * q * pop + arith + MASK_BYTES + _bit_bytes(q)) + n_solid * float(MASK_BYTES)
+    """Algorithmic bytes of one launch of the fluid pass: a fluid node reads and writes its q
+    populations, reads its cell word (and on D3Q27 its neighbour-bit word; in the FP16-storage
+    form its previous pseudopotential) and writes its pseudopotential; a solid node reads its cell
+    word and writes its pseudopotential (the wetting value).  Neighbour values are re-reads of the
+    same arrays and are not counted."""
+    fluid = 2 * q * pop + arith + MASK_BYTES + _bit_bytes(q) + (arith if pop == 2 else 0)
+    return n_fluid * fluid + n_solid * float(MASK_BYTES + arith)
 
 
 def copy_calibration(mib: int, reps: int) -> int:
@@ -88,7 +93,9 @@ def copy_calibration(mib: int, reps: int) -> int:
     return 0
 
 
-def traffic_from_profile(workload: str, precision: str, sha: str):
+def traffic_from_profile(workload: str, precision: str, sha: str, tile: dict):
+    """HBM bytes per launch of the fluid pass from the stored counter summary, when it was taken
+    on the same sources and tile shape (else None)."""
     path = os.path.join(ROOT, "profiles", f"{KERNEL}_{workload}_{precision}_hbm.json")
     if not os.path.exists(path):
         return None
@@ -96,6 +103,8 @@ def traffic_from_profile(workload: str, precision: str, sha: str):
         prof = json.load(f)
     if prof.get("source_sha") != sha:
         return None  # the kernel changed since the counters were taken
+    if prof.get("tile") != [tile.get("rows"), tile.get("planes")]:
+        return None  # counted on another launch shape
     return prof.get("hbm_bytes_per_launch")
 
 
@@ -351,19 +360,26 @@ def surrogate_run(args) -> int:
     return 0
 
 
-def tune_tile(sim, args) -> dict:
-    """Tile shape of the fluid pass: given (--tile), the library default (--no-autotune), or the
-    autotuner's choice (candidates timed on the live run before the warm-up; the state advances,
-    like warm-up steps)."""
-    if args.tile:
-        rows, planes = (int(v) for v in args.tile.split(","))
-        sim.set_tile(rows, planes)
-        return {"rows": rows, "planes": planes, "chosen_by": "given"}
-    if args.no_autotune:
+# Tile of the fluid pass timed by default on the 256^3 workload, per population storage: the
+# shapes the autotuner picked most often there (its candidates differ by a few per cent, within
+# run-to-run noise), fixed so that runs and the profiler's counters describe the same launch.
+# Other workloads run the library's default shape.
+DEFAULT_TILES = {"fp32": (8, 8), "fp16": (4, 8), "fp64": (4, 8)}
+
+
+def tune_tile(sim, args, precision: str, workload: str) -> dict:
+    """Tile shape of the fluid pass: given (--tile), the autotuner's choice (--autotune; candidates
+    timed on the live run before the warm-up, the state advancing like warm-up steps), the default
+    of the precision on the 256^3 workload, else the library's default."""
+    if args.autotune:
+        t = sim.autotune(5)
+        log(f"autotuned tile: {t}")
+        return {"rows": t["tile_rows"], "planes": t["chunk_planes"], "chosen_by": "autotune"}
+    if not args.tile and workload != "tetrahedron_drop":
         return {"chosen_by": "library default"}
-    t = sim.autotune(5)
-    log(f"autotuned tile: {t}")
-    return {"rows": t["tile_rows"], "planes": t["chunk_planes"], "chosen_by": "autotune"}
+    rows, planes = (int(v) for v in args.tile.split(",")) if args.tile else DEFAULT_TILES[precision]
+    sim.set_tile(rows, planes)
+    return {"rows": rows, "planes": planes, "chosen_by": "given" if args.tile else "default"}
 
 
 def main() -> int:
@@ -395,8 +411,10 @@ def main() -> int:
                     help="Adam steps on sweep + judged bridges after each judgement (0: none)")
     ap.add_argument("--tile", default=None, metavar="ROWS,PLANES",
                     help="tile shape of the fluid pass (default: the autotuner's choice)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="single-grid runs: time the tile candidates and keep the fastest instead of the default tile")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the library's default tile shape instead of autotuning it before the warm-up")
+                    help="batched sweep: keep the library's default tile shape of every instance instead of autotuning it")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only the FP64 CPU oracle: all host cores and one thread on each single-grid workload")
     args = ap.parse_args()
@@ -430,7 +448,7 @@ def main() -> int:
     log(f"workload {w.name} {w.shape} bodies={len(w.bodies)} {args.precision}")
     sim = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision=args.precision)
     stream = sim.stream
-    tile = tune_tile(sim, args)
+    tile = tune_tile(sim, args, args.precision, w.name)
 
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -457,7 +475,7 @@ def main() -> int:
     kb = kernel_bytes(n_fluid, n_solid, pop, arith, q)
     achieved = kb / (tm["kernel_ms"] / 1e3) / 1e9
     sha = source_sha()
-    traffic = traffic_from_profile(w.name, args.precision, sha) if q == 19 else None
+    traffic = traffic_from_profile(w.name, args.precision, sha, tile) if q == 19 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL,
                 "kernel_ms": round(tm["kernel_ms"], 5), "bytes_per_launch": kb}
@@ -472,7 +490,7 @@ def main() -> int:
         del sim
         torch.cuda.empty_cache()
         h = Simulation(w.params, w.bodies, w.rho0, w.phi0, precision="fp16")
-        htile = tune_tile(h, args)
+        htile = tune_tile(h, args, "fp16", w.name)
         h.step(args.warmup)
         torch.cuda.synchronize()
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -415,8 +415,24 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
         }
     };
     // the halo's inputs of plane zz straight into LDS buffer hb (DMA)
-    auto halo_issue = [&](int zz, int hb) {
-        if constexpr (DMA) {
+    // halo inputs of the plane in flight, where they go through registers (no DMA): prefetched one
+    // pass ahead in the FP16 form; the FP64 form, short of registers, loads them when it needs them
+    constexpr bool HPRE = !DMA && sizeof(S) == 2;
+    NodeIn<S, L> hin;
+    auto halo_load = [&](int zz, NodeIn<S, L> &o) {
+        const uint32_t hidx = halo_xy + pl * (uint32_t)wrapi(zz, nz);
+        const long long np = plane_stride();
+        o.m = mask[hidx];
+        o.pp = H ? psi_prev[hidx] : T(0);
+        const uint32_t is = hidx * (uint32_t)sizeof(S);
+        sfor<L::Q>([&](auto I) { o.v[I] = ldb(fin + (long long)I * np, is); });
+    };
+    // the halo's inputs of plane zz: straight into LDS buffer hb (DMA), else into registers
+    // (issued, not waited for; in the prologue, prefetch = false, halo_psi loads them itself)
+    auto halo_issue = [&](int zz, int hb, bool prefetch) {
+        if constexpr (!DMA) {
+            if (HPRE && prefetch && halo) halo_load(zz, hin);
+        } else {
             if (!halo) return;
             const uint32_t hidx = halo_xy + pl * (uint32_t)wrapi(zz, nz);
             const long long np = plane_stride();
@@ -429,8 +445,9 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
                                              (__attribute__((address_space(3))) void *)&lds.hmask[hb][hs], 4, 0, 0);
         }
     };
-    // psi of the halo entry of plane zz into the window: from the LDS buffer (DMA) or loaded now
-    auto halo_psi = [&](int zz) {
+    // psi of the halo entry of plane zz into the window: from the LDS buffer (DMA), from the
+    // registers prefetched one pass earlier (prefetched), or loaded now (prologue)
+    auto halo_psi = [&](int zz, bool prefetched) {
         if (!halo) return;
         T hp;
         if constexpr (DMA) {
@@ -438,14 +455,8 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
             hp = node_psi_of<S, L>(p, bodies, lds.hmask[hb][k], T(0),
                                    [&](auto I) { return lds.hpop[hb][decltype(I)::value][k]; });
         } else {
-            NodeIn<S, L> hi;
-            const uint32_t hidx = halo_xy + pl * (uint32_t)wrapi(zz, nz);
-            const long long np = plane_stride();
-            hi.m = mask[hidx];
-            hi.pp = H ? psi_prev[hidx] : T(0);
-            const uint32_t is = hidx * (uint32_t)sizeof(S);
-            sfor<L::Q>([&](auto I) { hi.v[I] = ldb(fin + (long long)I * np, is); });
-            hp = node_psi_of<S, L>(p, bodies, hi.m, hi.pp, [&](auto I) { return hi.v[decltype(I)::value]; });
+            if (!(HPRE && prefetched)) halo_load(zz, hin);
+            hp = node_psi_of<S, L>(p, bodies, hin.m, hin.pp, [&](auto I) { return hin.v[decltype(I)::value]; });
         }
         lds.ring[slot(zz)][hly + 1][hlx + 1] = win_entry<S>(hp, p.rho0);
     };
@@ -462,14 +473,14 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
     // flight
     load_own(zs - 1, A);
     own_psi(zs - 1, A);
-    halo_issue(zs - 1, hbuf(zs - 1));
-    halo_issue(zs, hbuf(zs));
+    halo_issue(zs - 1, hbuf(zs - 1), false);
+    halo_issue(zs, hbuf(zs), false);
     load_own(zs, A);
     load_own(zs + 1, B);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    halo_psi(zs - 1);
-    halo_psi(zs);
+    halo_psi(zs - 1, false);
+    halo_psi(zs, false);
     own_psi(zs, A);
 #pragma unroll
     for (int r = 0; r < RPT; ++r) sfor<L::Q>([&](auto I) { lds.pop[I][tid + 64 * W * r] = A[r].v[I]; });
@@ -480,19 +491,19 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
         cm[r] = A[r].m;
         cpp[r] = A[r].pp;
     }
-    halo_issue(zs + 1, hbuf(zs + 1));
+    halo_issue(zs + 1, hbuf(zs + 1), true);
     for (int z = zs; z < ze; ++z) {
         // plane z + 1 has landed (own populations in B, halo in its LDS buffer); every wave is done
         // with the previous plane's window entries and halo buffer
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         own_psi(z + 1, B);
-        halo_psi(z + 1);
+        halo_psi(z + 1, true);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) A[r] = B[r];
         if (z + 2 <= ze) {
             load_own(z + 2, B);
-            halo_issue(z + 2, hbuf(z + 2));
+            halo_issue(z + 2, hbuf(z + 2), true);
         }
         __syncthreads();
         const uint32_t zo = pl * (uint32_t)z;

@@ -106,6 +106,20 @@ def test_plates_bridge_fp32_200_steps(oracle_mod, torch_cuda):
     compare(sim, ref, 200, force_scale=math.pi * SIGMA * 6.0, lever=8.0, **FP32)
 
 
+@pytest.mark.parametrize("shape", [(20, 24, 28), (13, 17, 30)])
+def test_tiles_follow_a_fast_body_fp64(oracle_mod, torch_cuda, shape):
+    """A sphere crossing many 8x8x4 phase-field tiles (about 20 cells in 120 steps, rotating)
+    beside a resting one: tiles turn active ahead of it and idle behind it, and the FP64 build
+    stays at round-off against the oracle.  The second grid has last tiles of 1 node in y and z,
+    where a tile's activity reaches two tiles out."""
+    w = tiny_moving_body(shape=shape, v=(0.15, -0.08, 0.1), w=(0.01, 0.0, 0.02), second_body=True)
+    w.params["e0"] = 0.5
+    sim, ref = _pair(oracle_mod, w, 120, "fp64")
+    compare(sim, ref, 120, lever=3.0, **FP64)
+    dg, do = sim.diag(), ref.diag()
+    assert dg["n_f2s"] == do["n_f2s"] and dg["n_s2f"] == do["n_s2f"] and dg["n_f2s"] > 50
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
 @pytest.mark.parametrize("cap", [0, 1])
 def test_event_list_overflow_path(oracle_mod, torch_cuda, precision, cap):
