@@ -67,13 +67,6 @@ template <typename T>
 __device__ __forceinline__ T ldb(const T *base, uint32_t byteoff) {
     return *(const T *)((const char *)base + byteoff);
 }
-// non-temporal load: for data a pass reads exactly once (measured on the collide-stream pass:
-// its population loads marked so leave L2 to the pseudopotential gathers and to the pushed
-// stores, which the next pass reads; 81.6 -> 67.3 us per launch on the 128^3 workload)
-template <typename T>
-__device__ __forceinline__ T ldb_nt(const T *base, uint32_t byteoff) {
-    return __builtin_nontemporal_load((const T *)((const char *)base + byteoff));
-}
 template <typename T>
 __device__ __forceinline__ void stb(T *base, uint32_t byteoff, T v) {
     *(T *)((char *)base + byteoff) = v;

@@ -578,12 +578,10 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
         }
     }
     const long long vol0 = any ? (long long)(box[3] - box[0] + 1) * (box[4] - box[1] + 1) * (box[5] - box[2] + 1) : 0;
-    // box kernels: about one thread per cell of the initial box with room to grow (grid-stride
-    // loops cover larger boxes), at most 4096 blocks
-    const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
     // box kernels: one tile of 256 nodes per block, about one block per tile of the initial box
-    // with room to grow (larger boxes are covered by grid-stride loops): each tile's work is a
-    // short chain of dependent loads, which many resident blocks overlap
+    // with room to grow, at most 4096 (larger boxes are covered by grid-stride loops): each tile's
+    // work is a short chain of dependent loads, which many resident blocks overlap
+    const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
     const int box_grid = box_blocks;
     const int force_grid = std::min((box_blocks + 3) / 4, FORCE_GRID_MAX);
     // phase update (and the classification partials it leaves): grid-stride over the tiles with

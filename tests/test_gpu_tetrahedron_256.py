@@ -3,8 +3,8 @@ vertices of a regular tetrahedron, central drop of 5 %, seeded 1e-3 perturbation
 fields, the paper's tau = 1.1) against the FP64 oracle, element by element after a 4-step slice
 (the oracle takes a few CPU seconds per step at this size).
 
-This is the launch configuration the benchmark times (1024-block box kernels, four bodies, the
-whole 256^3 grid).  Bars (parity_helpers documents how each figure is measured):
+This is the launch configuration the benchmark times (the fluid pass over the whole 256^3 grid,
+four bodies, the phase-field kernels on the active tiles of the box).  Bars (parity_helpers documents how each figure is measured):
   FP64         fields <= 1e-11 (relative L2), 1e-10 per node; body quantities <= 1e-9
   FP32         fields <= 1e-5, 1e-4 per node; body quantities <= 1e-4
   FP16 storage body quantities <= 1e-3 (force over max(|F_oracle|, pi sigma R)); density
