@@ -109,6 +109,13 @@ constexpr bool wall_in_fluid_pass() {
     return sizeof(S) == 2;
 }
 
+// Motion of every body for the moving-wall term of the FP16 form, staged in LDS by the fluid pass
+// (centre FP64 for the minimum-image lever arm, velocities as the FP32 arithmetic uses them).
+struct WallMot {
+    double X[PF_LBM_MAX_BODIES][3];
+    float V[PF_LBM_MAX_BODIES][3], W[PF_LBM_MAX_BODIES][3];
+};
+
 // psin(I): psi of the neighbour in direction I; FP16 form: refn(I) its reference density R (the
 // encode of a population pushed there) and rown the node's own (the encode of its own slots),
 // both R(psi) of this step's psi, formed once per node with the window
@@ -117,7 +124,7 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
                                              ArT<S> psi0, ArT<S> rown, S *__restrict__ fout, uint32_t solid_dirs,
                                              int x, int y, int z,
                                              long long Np, const cell_t *__restrict__ mask,
-                                             const BodyDev *__restrict__ bodies) {
+                                             const WallMot *wm) {
     using T = ArT<S>;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const uint32_t idx = (uint32_t)(x + nx * (y + ny * z));
@@ -219,7 +226,8 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
         });
     } else {
         // f*_i + g_i into slot opp(i), g_i = -2 rho w_i (c_i . u_w) / c_s^2 with u_w the rigid
-        // velocity at the link midpoint x + c_i / 2; the rest population gives back the g_i
+        // velocity at the link midpoint x + c_i / 2; the rest population gives back the g_i.  The
+        // bodies' motion comes from LDS, so a link waits for one load (the neighbour's owner).
         const NbrU ne(x, y, z, nx, ny, nz, 1);
         sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
@@ -229,13 +237,13 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
                 } else {
                     // the FP16 form's collision arithmetic is FP32: the lever arm about the body
                     // centre (minimum image, FP64) and the wall velocity at the link midpoint in FP32
-                    const BodyDev &Bd = bodies[owner_of(mask[ne.template at<i>(idx)])];
-                    const T rx = (T)mimg_r(x - Bd.X[0], nx, p.inv_n[0]) + T(0.5 * Dir<i, L>::x),
-                            ry = (T)mimg_r(y - Bd.X[1], ny, p.inv_n[1]) + T(0.5 * Dir<i, L>::y),
-                            rz = (T)mimg_r(z - Bd.X[2], nz, p.inv_n[2]) + T(0.5 * Dir<i, L>::z);
-                    const T wx = (T)Bd.W[0], wy = (T)Bd.W[1], wz = (T)Bd.W[2];
-                    const T uwx = (T)Bd.V[0] + (wy * rz - wz * ry), uwy = (T)Bd.V[1] + (wz * rx - wx * rz),
-                            uwz = (T)Bd.V[2] + (wx * ry - wy * rx);
+                    const int o = owner_of(mask[ne.template at<i>(idx)]);
+                    const T rx = (T)mimg_r(x - wm->X[o][0], nx, p.inv_n[0]) + T(0.5 * Dir<i, L>::x),
+                            ry = (T)mimg_r(y - wm->X[o][1], ny, p.inv_n[1]) + T(0.5 * Dir<i, L>::y),
+                            rz = (T)mimg_r(z - wm->X[o][2], nz, p.inv_n[2]) + T(0.5 * Dir<i, L>::z);
+                    const T wx = wm->W[o][0], wy = wm->W[o][1], wz = wm->W[o][2];
+                    const T uwx = wm->V[o][0] + (wy * rz - wz * ry), uwy = wm->V[o][1] + (wz * rx - wx * rz),
+                            uwz = wm->V[o][2] + (wx * ry - wy * rx);
                     const T cuw = T(Dir<i, L>::x) * uwx + T(Dir<i, L>::y) * uwy + T(Dir<i, L>::z) * uwz;
                     const T gw = T(-6.0 * Dir<i, L>::template w<double>()) * cuw * rho;
                     stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
@@ -282,6 +290,7 @@ struct FluidLds {
     // halo entries: the rows below and above the tile (64 each), the two columns (TY + 2 each)
     static constexpr int NH = DMA ? 128 + 2 * (TY + 2) : 1, NB = DMA ? 2 : 1;
     WinE<S> ring[3][TY + 2][66];
+    std::conditional_t<wall_in_fluid_pass<S>(), WallMot, char> wm;  // bodies' motion (FP16 form)
     S pop[L::Q][64 * TY];
     S hpop[NB][L::Q][NH];
     cell_t hmask[NB][NH];
@@ -356,6 +365,25 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
     const int tid = (int)threadIdx.x, tx = tid & 63, wv = tid >> 6;
     if (cpart && blockIdx.x == 0)
         publish_step_state(wv, W, parity, p.nx, p.ny, p.nz, p.nb, p.eta, st, bodies, cpart, cblk);
+    // FP16 form: the bodies' motion for the moving-wall term into LDS (ordered before its first
+    // use by the prologue's barrier)
+    if constexpr (wall_in_fluid_pass<S>()) {
+        for (int k = tid; k < p.nb * 9; k += 64 * W) {
+            const int b = k / 9, c = k % 9;
+            if (c < 3)
+                lds.wm.X[b][c] = bodies[b].X[c];
+            else if (c < 6)
+                lds.wm.V[b][c - 3] = (float)bodies[b].V[c - 3];
+            else
+                lds.wm.W[b][c - 6] = (float)bodies[b].W[c - 6];
+        }
+    }
+    auto wall_mot = [&]() -> const WallMot * {
+        if constexpr (wall_in_fluid_pass<S>())
+            return &lds.wm;
+        else
+            return nullptr;
+    };
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int tiles_x = (nx + 63) / 64, tiles_y = (ny + TY - 1) / TY, tiles = tiles_x * tiles_y;
     const int b = xcd_block((int)blockIdx.x, (int)gridDim.x);
@@ -543,7 +571,7 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
                     collide_push<S, L>(
                         p, cur, rin, [&](auto I) { return win_psi<S>(nbr(I)); },
                         [&](auto I) { return win_ref<S>(nbr(I)); }, psi0, win_ref<S>(*r0), fout, solid_dirs, x,
-                        y0 + ty, z, plane_stride(), mask, bodies);
+                        y0 + ty, z, plane_stride(), mask, wall_mot());
                 }
             }
             cm[r] = A[r].m;
