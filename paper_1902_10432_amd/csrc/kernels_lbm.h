@@ -227,8 +227,8 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
     } else {
         // f*_i + g_i into slot opp(i), g_i = -2 rho w_i (c_i . u_w) / c_s^2 with u_w the rigid
         // velocity at the link midpoint x + c_i / 2; the rest population gives back the g_i.  The
-        // bodies' motion comes from LDS, so a link waits for one load (the neighbour's owner).
-        const NbrU ne(x, y, z, nx, ny, nz, 1);
+        // solid neighbour's owner comes from its window entry and the bodies' motion from LDS, so
+        // the links wait for no global load.
         sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0) {
@@ -237,7 +237,8 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
                 } else {
                     // the FP16 form's collision arithmetic is FP32: the lever arm about the body
                     // centre (minimum image, FP64) and the wall velocity at the link midpoint in FP32
-                    const int o = owner_of(mask[ne.template at<i>(idx)]);
+                    // (bounded to the body table whatever the entry holds)
+                    const int o = __float_as_int(refn(I)) & (PF_LBM_MAX_BODIES - 1);
                     const T rx = (T)mimg_r(x - wm->X[o][0], nx, p.inv_n[0]) + T(0.5 * Dir<i, L>::x),
                             ry = (T)mimg_r(y - wm->X[o][1], ny, p.inv_n[1]) + T(0.5 * Dir<i, L>::y),
                             rz = (T)mimg_r(z - wm->X[o][2], nz, p.inv_n[2]) + T(0.5 * Dir<i, L>::z);
@@ -259,8 +260,10 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
 // tile's populations of the plane being collided ([direction][node of the tile], stored form),
 // and, where the budget allows (DMA), the halo's populations, cell words and previous psi of
 // two planes, loaded straight into LDS.
-// entry of the psi window: psi, and in the FP16 form beside it the reference density R(psi) of the
-// node (formed once per node instead of once per population pushed to it)
+// entry of the psi window: psi, and in the FP16 form beside it the reference density R(psi) of a
+// fluid node (formed once per node instead of once per population pushed to it) or, for a solid
+// node (never a push destination), the index of its owner as an integer bit pattern (the moving-
+// wall term of a link into it reads the owner from the window instead of the cell word)
 template <typename S>
 using WinE = std::conditional_t<sizeof(S) == 2, float2, ArT<S>>;
 template <typename S>
@@ -278,9 +281,9 @@ __device__ __forceinline__ ArT<S> win_ref(const WinE<S> &e) {
         return ArT<S>(0);
 }
 template <typename S>
-__device__ __forceinline__ WinE<S> win_entry(ArT<S> psi, ArT<S> rho0) {
+__device__ __forceinline__ WinE<S> win_entry(ArT<S> psi, ArT<S> rho0, cell_t m) {
     if constexpr (sizeof(S) == 2)
-        return make_float2(psi, ref_density(psi, rho0));
+        return make_float2(psi, (m & C_SOLID) ? __int_as_float(owner_of(m)) : ref_density(psi, rho0));
     else
         return psi;
 }
@@ -478,22 +481,24 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
     auto halo_psi = [&](int zz, bool prefetched) {
         if (!halo) return;
         T hp;
+        cell_t hm;
         if constexpr (DMA) {
             const int hb = hbuf(zz), k = hs + tx;
-            hp = node_psi_of<S, L>(p, bodies, lds.hmask[hb][k], T(0),
-                                   [&](auto I) { return lds.hpop[hb][decltype(I)::value][k]; });
+            hm = lds.hmask[hb][k];
+            hp = node_psi_of<S, L>(p, bodies, hm, T(0), [&](auto I) { return lds.hpop[hb][decltype(I)::value][k]; });
         } else {
             if (!(HPRE && prefetched)) halo_load(zz, hin);
+            hm = hin.m;
             hp = node_psi_of<S, L>(p, bodies, hin.m, hin.pp, [&](auto I) { return hin.v[decltype(I)::value]; });
         }
-        lds.ring[slot(zz)][hly + 1][hlx + 1] = win_entry<S>(hp, p.rho0);
+        lds.ring[slot(zz)][hly + 1][hlx + 1] = win_entry<S>(hp, p.rho0, hm);
     };
     auto own_psi = [&](int zz, const NodeIn<S, L> (&o)[RPT]) {
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
             lds.ring[slot(zz)][wv + W * r + 1][tx + 1] = win_entry<S>(
                 node_psi_of<S, L>(p, bodies, o[r].m, o[r].pp, [&](auto I) { return o[r].v[decltype(I)::value]; }),
-                p.rho0);
+                p.rho0, o[r].m);
     };
 
     NodeIn<S, L> A[RPT], B[RPT];
