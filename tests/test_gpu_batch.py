@@ -56,20 +56,23 @@ def test_batch_matches_individual_runs(torch_cuda):
             assert np.array_equal(x, y)
 
 
-def test_batch_graph_matches_individual_runs(torch_cuda):
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_batch_graph_matches_individual_runs(torch_cuda, precision):
     """All instances captured into one HIP graph (4 steps per replay) and replayed: per instance
     the same bits as stepping it alone, also across an instance stepped on its own in between
-    (parity change forces a new capture) and a remainder that is not a whole replay."""
+    (parity change forces a new capture), a new tile shape on one instance (forces a new capture
+    too) and a remainder that is not a whole replay."""
     from paper_1902_10432_amd.simulation import Batch
     ws = [bridge_pair(*args) for args in SMALL]
-    _print("case batch graph of " + ", ".join(str(w.shape) for w in ws))
-    alone = [_sim(w) for w in ws]
+    _print(f"case batch graph of " + ", ".join(str(w.shape) for w in ws) + f" {precision}")
+    alone = [_sim(w, precision) for w in ws]
     for s in alone:
         s.step(31)
-    together = [_sim(w) for w in ws]
+    together = [_sim(w, precision) for w in ws]
     b = Batch(together, graph_steps=4)
     b.step(12)
     together[1].step(3)
+    together[2].set_tile(4, 8)
     b.step(8)
     together[0].step(3)
     together[2].step(3)
