@@ -193,19 +193,22 @@ __device__ __forceinline__ float ref_density(float psi, float rho0) {
     return -0.69314718f * rho0 * __log2f(q);
 }
 
-// stored value -> population, with wref = w_i R
+// stored value -> population, with weight w = w_i and reference density R: the FP16 form holds
+// the deviation f - w R.  Both directions are one explicit fused multiply-add (a single rounding
+// of w R + v and of f - w R), so the encode does not depend on how the compiler contracts the
+// surrounding arithmetic.
 template <typename S>
-__device__ __forceinline__ ArT<S> pop_get(S v, ArT<S> wref) {
+__device__ __forceinline__ ArT<S> pop_get(S v, ArT<S> w, ArT<S> R) {
     if constexpr (sizeof(S) == 2)
-        return wref + (float)v;
+        return __builtin_fmaf(w, R, (float)v);
     else
         return v;
 }
 // population -> stored value
 template <typename S>
-__device__ __forceinline__ S pop_put(ArT<S> f, ArT<S> wref) {
+__device__ __forceinline__ S pop_put(ArT<S> f, ArT<S> w, ArT<S> R) {
     if constexpr (sizeof(S) == 2)
-        return (S)(f - wref);
+        return (S)__builtin_fmaf(-w, R, f);
     else
         return f;
 }

@@ -133,7 +133,7 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
     constexpr bool H = sizeof(S) == 2;  // FP16 storage: deviations from w_i R
 
     T f[L::Q];
-    sfor<L::Q>([&](auto I) { f[I] = pop_get<S>(sv[I], Dir<decltype(I)::value, L>::template w<T>() * rin); });
+    sfor<L::Q>([&](auto I) { f[I] = pop_get<S>(sv[I], Dir<decltype(I)::value, L>::template w<T>(), rin); });
     // moments from pair sums and differences
     T rho = f[0], jx = T(0), jy = T(0), jz = T(0);
     sfor<(L::Q - 1) / 2>([&](auto K) {
@@ -211,7 +211,7 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
         sfor<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0)
-                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * refn(I)));
+                stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>(), refn(I)));
         });
     } else if constexpr (!wall_in_fluid_pass<S>()) {
         // f*_i into slot opp(i); the force scan adds the moving-wall term and the mass correction
@@ -219,9 +219,9 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0) {
                 if (!(solid_dirs & (1u << i)))
-                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * refn(I)));
+                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>(), refn(I)));
                 else
-                    stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i], Dir<i, L>::template w<T>() * rown));
+                    stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i], Dir<i, L>::template w<T>(), rown));
             }
         });
     } else {
@@ -233,7 +233,7 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
             constexpr int i = decltype(I)::value;
             if constexpr (i > 0) {
                 if (!(solid_dirs & (1u << i))) {
-                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>() * refn(I)));
+                    stb(fout + (long long)i * Np, ns.template at<i>(is), pop_put<S>(f[i], Dir<i, L>::template w<T>(), refn(I)));
                 } else {
                     // the FP16 form's collision arithmetic is FP32: the lever arm about the body
                     // centre (minimum image, FP64) and the wall velocity at the link midpoint in FP32
@@ -247,13 +247,13 @@ __device__ __forceinline__ void collide_push(const Prm<ArT<S>> &p, const S *sv, 
                             uwz = wm->V[o][2] + (wx * ry - wy * rx);
                     const T cuw = T(Dir<i, L>::x) * uwx + T(Dir<i, L>::y) * uwy + T(Dir<i, L>::z) * uwz;
                     const T gw = T(-6.0 * Dir<i, L>::template w<double>()) * cuw * rho;
-                    stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>() * rown));
+                    stb(fout + (long long)Dir<i, L>::opp * Np, is, pop_put<S>(f[i] + gw, Dir<i, L>::template w<T>(), rown));
                     drho += gw;
                 }
             }
         });
     }
-    stb(fout, is, pop_put<S>(f[0] - drho, Dir<0, L>::template w<T>() * rown));
+    stb(fout, is, pop_put<S>(f[0] - drho, Dir<0, L>::template w<T>(), rown));
 }
 
 // LDS of the fluid pass: the psi window (3 planes of the tile and its halo, 66 x (TY + 2)), the
@@ -699,7 +699,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                                 own[i >> 3] |= o << (4 * (i & 7));
                                 touched |= 1u << o;
                                 // reflected value: f*_i, or f*_i + g_i where the fluid pass added g
-                                fr[i] = pop_get<S>(fo[i], Dir<i, L>::template w<T>() * rown);
+                                fr[i] = pop_get<S>(fo[i], Dir<i, L>::template w<T>(), rown);
                                 a[i] = T(2) * fr[i] + gp * Dir<i, L>::template w<T>() * pn[i];
                             }
                         }
@@ -750,7 +750,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                             double s;
                             if constexpr (!wall_in_fluid_pass<S>()) {
                                 stb(fpost + (long long)Dir<i, L>::opp * Np, (uint32_t)idx * (uint32_t)sizeof(S),
-                                    pop_put<S>(fr[i] + g, Dir<i, L>::template w<T>() * rown));
+                                    pop_put<S>(fr[i] + g, Dir<i, L>::template w<T>(), rown));
                                 drho += g;
                                 s = (double)(a[i] + g);
                             } else {
@@ -828,8 +828,8 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
         if (!wall_in_fluid_pass<S>() && fluid && nbits) {
             // the rest population gives back the moving-wall terms (mass correction, Sec. 3.2.2)
             const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
-            const T f0 = pop_get<S>(ldb(fpost, is), Dir<0, L>::template w<T>() * rown);
-            stb(fpost, is, pop_put<S>(f0 - drho, Dir<0, L>::template w<T>() * rown));
+            const T f0 = pop_get<S>(ldb(fpost, is), Dir<0, L>::template w<T>(), rown);
+            stb(fpost, is, pop_put<S>(f0 - drho, Dir<0, L>::template w<T>(), rown));
         }
     }
     __syncthreads();

@@ -800,7 +800,7 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
     T acc[L::Q];
     sfor<L::Q>([&](auto I) {
         acc[I] = (m & C_S2F) ? T(0)
-                             : pop_get<S>(f[(long long)I * Np + idx], Dir<decltype(I)::value, L>::template w<T>() * rr);
+                             : pop_get<S>(f[(long long)I * Np + idx], Dir<decltype(I)::value, L>::template w<T>(), rr);
     });
     // sources in increasing offset order; the loop runs per lane over its own sources only (a loop
     // over all 26 offsets would run, in a wave, over the union of its lanes' sources)
@@ -816,7 +816,7 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
         T fs[L::Q];
         const T rn = H ? ref_density(psi[n], p.rho0) : T(0);
         sfor<L::Q>([&](auto I) {
-            fs[I] = pop_get<S>(f[(long long)I * Np + n], Dir<decltype(I)::value, L>::template w<T>() * rn);
+            fs[I] = pop_get<S>(f[(long long)I * Np + n], Dir<decltype(I)::value, L>::template w<T>(), rn);
         });
         T rho = T(0), jx = T(0), jy = T(0), jz = T(0);
         sfor<L::Q>([&](auto I) {
@@ -836,7 +836,7 @@ __device__ void gather_receiver(const Prm<ArT<S>> &p, const cell_t *__restrict__
         sfor<L::Q>([&](auto I) { acc[I] += feq_dir<T, decltype(I)::value, L>(rho, vx, vy, vz) * inv; });
     }
     sfor<L::Q>([&](auto I) {
-        f[(long long)I * Np + idx] = pop_put<S>(acc[I], Dir<decltype(I)::value, L>::template w<T>() * rr);
+        f[(long long)I * Np + idx] = pop_put<S>(acc[I], Dir<decltype(I)::value, L>::template w<T>(), rr);
     });
 }
 
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(256) void k_convert_gather(Prm<ArT<S>> p, int parit
             if ((ne.centre & C_S2F) && !ne.f2s(0xFFFFFFFFu)) {
                 const T re = sizeof(S) == 2 ? ref_density(psi[e], p.rho0) : T(0);
                 sfor<L::Q>([&](auto I) {
-                    f[(long long)I * Np + e] = pop_put<S>(T(0), Dir<decltype(I)::value, L>::template w<T>() * re);
+                    f[(long long)I * Np + e] = pop_put<S>(T(0), Dir<decltype(I)::value, L>::template w<T>(), re);
                 });
             }
             continue;
@@ -929,7 +929,7 @@ __device__ __forceinline__ void refresh_node(const Prm<ArT<S>> &p, cell_t *mask,
 #pragma unroll 1
         for (int i = 0; i < L::Q; ++i) {
             const int c2 = kCX[i] * kCX[i] + kCY[i] * kCY[i] + kCZ[i] * kCZ[i];
-            f[(long long)i * p.Np + idx] = pop_put<S>(T(0), T(L::wshell[c2]) * rr);
+            f[(long long)i * p.Np + idx] = pop_put<S>(T(0), T(L::wshell[c2]), rr);
         }
     }
     uint32_t bits = 0;
@@ -1043,7 +1043,7 @@ __global__ void k_init_f(Prm<ArT<S>> p, const double *__restrict__ rho, const ce
         const T rr = sizeof(S) == 2 ? ref_density(ps, p.rho0) : T(0);
         sfor<L::Q>([&](auto I) {
             constexpr T w = Dir<decltype(I)::value, L>::template w<T>();
-            fa[(long long)I * p.Np + idx] = pop_put<S>(w * r, w * rr);
+            fa[(long long)I * p.Np + idx] = pop_put<S>(w * r, w, rr);
         });
     }
 }
@@ -1074,7 +1074,7 @@ __global__ void k_fields(Prm<ArT<S>> p, int which, const S *__restrict__ f, cons
             sfor<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const double c = which == 0 ? 1.0 : (which == 1 ? Dir<i, L>::x : (which == 2 ? Dir<i, L>::y : Dir<i, L>::z));
-                s += c * (double)pop_get<S>(f[(long long)i * p.Np + idx], Dir<i, L>::template w<T>() * rr);
+                s += c * (double)pop_get<S>(f[(long long)i * p.Np + idx], Dir<i, L>::template w<T>(), rr);
             });
             out = s;
         }
