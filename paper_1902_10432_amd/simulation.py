@@ -86,7 +86,12 @@ class Simulation:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # at interpreter shutdown the binding module may already be torn down; the process
+        # releases the handle with it
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def _check(self, rc):
         if rc != B.PF_LBM_OK:
@@ -186,4 +191,7 @@ class Batch:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -120,7 +120,10 @@ class Surrogate:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _load().pf_mlp_destroy(h)
+            try:  # the binding may already be torn down at interpreter shutdown
+                _load().pf_mlp_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
 
@@ -242,5 +245,8 @@ class SphereRun:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _load_dem().pf_dem_destroy(h)
+            try:  # the binding may already be torn down at interpreter shutdown
+                _load_dem().pf_dem_destroy(h)
+            except Exception:
+                pass
             self._h = None
