@@ -120,6 +120,32 @@ def test_tiles_follow_a_fast_body_fp64(oracle_mod, torch_cuda, shape):
     assert dg["n_f2s"] == do["n_f2s"] and dg["n_s2f"] == do["n_s2f"] and dg["n_f2s"] > 50
 
 
+def test_trapped_cavity_content_is_lost_fp64(oracle_mod, torch_cuda):
+    """A single fluid node inside a resting solid cube (phase 0.9499 against the 0.95 threshold,
+    filled with liquid) turns solid under the kinetics; no fluid node lies within sqrt 3 to take
+    its content, so the conversion counts it as lost (Sec. 3.2.2 gives no receiver).  The GPU's
+    count of such nodes and every field match the FP64 oracle."""
+    from paper_1902_10432_amd.simulation import Simulation
+    from pflbm_inputs.coexistence import coexistence_densities
+    from pflbm_inputs.params import default_params
+    from pflbm_inputs.workloads import Workload
+    shape = (10, 10, 10)
+    rv, rl = coexistence_densities()
+    phi = np.zeros((1,) + shape)
+    phi[0, 2:8, 2:8, 2:8] = 1.0
+    phi[0, 5, 5, 5] = 0.9499
+    rho = np.full(shape, rv)
+    rho[5, 5, 5] = rl
+    bodies = [{"mass_density": 4.0, "wetting_rho": 1.2, "v": (0.0, 0.0, 0.0), "w": (0.0, 0.0, 0.0), "fixed": 1}]
+    w = Workload("trapped_cavity", default_params(10, 10, 10, 1, motion=0), bodies, rho, phi)
+    sim, ref = _pair(oracle_mod, w, 25, "fp64")
+    # the cube sits symmetric in vapour: its net force is round-off, measured against pi sigma
+    compare(sim, ref, 25, force_scale=math.pi * SIGMA, lever=3.0, **FP64)
+    dg, do = sim.diag(), ref.diag()
+    assert do["n_f2s"] == 1 and do["lost_mass"] == pytest.approx(rl, rel=1e-12)
+    assert dg["n_f2s"] == 1 and dg["n_lost"] == 1
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
 @pytest.mark.parametrize("cap", [0, 1])
 def test_event_list_overflow_path(oracle_mod, torch_cuda, precision, cap):
