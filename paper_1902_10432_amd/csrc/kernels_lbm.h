@@ -585,7 +585,7 @@ __global__ __launch_bounds__(64 * FluidShape<TY>::W) void k_collide_stream(Prm<A
     }
 }
 
-// Per-body force and torque sums of the step, one box node per thread (Sec. 3.1.1, 3.1.2, 3.2.2):
+// Per-body force and torque sums of the step over the box nodes (Sec. 3.1.1, 3.1.2, 3.2.2):
 //  * fluid nodes next to solid nodes: the fluid pass reflected each population f*_i heading into
 //    a solid node into the node's opposite slot; unless the fluid pass did so (wall_in_fluid_pass),
 //    this kernel completes the moving-wall bounce-back of Sec. 3.2.2 there -- the slot becomes
@@ -638,199 +638,255 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
     const bool rep = nbod > 1 && (p.flags & PF_LBM_REPULSION);
     const double rc = p.r_c;
     constexpr int RC = 16;  // repulsion offsets per round of loads
-    for (int base = blockIdx.x * NT; base < it.vol; base += gridDim.x * NT) {
-        const int k = base + tid;
-        uint32_t touched = 0;
-        int x = 0, y = 0, z = 0, idx = 0, b1 = -1;
-        uint32_t nbits = 0;  // solid-neighbour bits of a fluid node
-        bool fluid = false;
-        T rho = T(0), ps0 = T(0), rown = T(0), drho = T(0);
-        // per link i into a solid neighbour: its owner (4-bit fields), the reflected post-collision
-        // population fr_i = f*_i and the body-independent part of the link force, a_i = 2 f*_i +
-        // G psi(x) w_i psi(x + c_i); drho sums the moving-wall terms of the node's links
-        uint32_t own[(L::Q + 7) / 8] = {};
-        T a[L::Q], fr[L::Q];
-        if (k < it.vol) {
-            int u[3], c[3];
-            it.cell(k, u, c);
-            x = c[0];
-            y = c[1];
-            z = c[2];
-            idx = x + nx * (y + ny * z);
-            const cell_t w0 = mask[idx];
-            if (!(w0 & C_SOLID)) {
-                fluid = true;
-                uint32_t mo[L::Q];  // words of the neighbours
-                const NbrU ne(x, y, z, nx, ny, nz, 1);
+    // Each wave takes runs of 64 U consecutive box cells.  A first pass loads their cell words in
+    // one round and keeps the cells that need the per-link (or repulsion) work: fluid cells with a
+    // solid neighbour, and solid cells within r_c of the solid radius of a higher-index body.  The
+    // second pass runs that work on the kept cells only, 64 per round, so the cells without a link
+    // cost one load in a wide round instead of a pass of the scan each.
+    constexpr int U = 8;
+    __shared__ int keep[W][64 * U];
+    const int gw = (int)blockIdx.x * W + wave, nw = (int)gridDim.x * W;
+    for (int run = gw * 64 * U; run < it.vol; run += nw * 64 * U) {
+        int nkeep = 0;
+        {
+            cell_t wk[U];
+            int ck[U][3];
+            bool in[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = run + 64 * u + lane;
+                in[u] = k < it.vol;
+                int uu[3];
+                it.cell(in[u] ? k : 0, uu, ck[u]);
+                wk[u] = in[u] ? mask[ck[u][0] + nx * (ck[u][1] + ny * ck[u][2])] : cell_t(C_SOLID);
+            }
+            uint32_t nbk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 if constexpr (L::kBits)
-                    nbits = w0 & C_NBMASK;
+                    nbk[u] = wk[u] & C_NBMASK;
                 else
-                    nbits = nbw[idx];
-                if (nbits) {
-                    // Every gather of the node is issued in one round and unconditionally (the
-                    // neighbour values are cache-served), so the per-link selects below wait for
-                    // memory once; loads inside the per-link branches were serialised, one
-                    // memory latency per link.
-                    const uint32_t ib = (uint32_t)idx * (uint32_t)sizeof(T);
-                    const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
-                    S fo[L::Q];  // reflected populations f*_i, in slot opp(i), written by the fluid pass
-                    T pn[L::Q];  // neighbour pseudopotentials
-                    sfor<L::Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        if constexpr (i > 0) {
-                            const uint32_t n = ne.template at<i>((uint32_t)idx);
-                            mo[i] = ldb(mask, n * 4u);
-                            fo[i] = ldb(fpost + (long long)Dir<i, L>::opp * Np, is);
-                            pn[i] = ldb(psi, n * (uint32_t)sizeof(T));
+                    nbk[u] = (in[u] && !(wk[u] & C_SOLID)) ? nbw[ck[u][0] + nx * (ck[u][1] + ny * ck[u][2])] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                bool need = false;
+                if (in[u]) {
+                    if (!(wk[u] & C_SOLID)) {
+                        need = nbk[u] != 0;
+                    } else if (rep) {
+                        const int o1 = owner_of(wk[u]);
+                        for (int b2 = o1 + 1; b2 < nbod; ++b2) {
+                            const double *BX = bt[wave][b2];
+                            const double rx = mimg_r(ck[u][0] - BX[0], nx, p.inv_n[0]),
+                                         ry = mimg_r(ck[u][1] - BX[1], ny, p.inv_n[1]),
+                                         rz = mimg_r(ck[u][2] - BX[2], nz, p.inv_n[2]);
+                            if (sqrt(rx * rx + ry * ry + rz * rz) < (double)st->srad[b2] + rc + 1e-3) need = true;
                         }
-                    });
-                    rho = sizeof(S) == 2 ? ref_density(psi_prev[idx], p.rho0) : T(0);
-                    sfor<L::Q>([&](auto I) { rho += (T)ldb(fin + (long long)I * Np, is); });
-                    ps0 = ldb(psi, ib);
-                    rown = sizeof(S) == 2 ? ref_density(ps0, p.rho0) : T(0);
-                    const T gp = p.G * ps0;
-                    sfor<L::Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        a[i] = T(0);
-                        fr[i] = T(0);
-                        if constexpr (i > 0) {
-                            if (nbits & (1u << i)) {
-                                const uint32_t o = (uint32_t)owner_of(mo[i]);
-                                own[i >> 3] |= o << (4 * (i & 7));
-                                touched |= 1u << o;
-                                // reflected value: f*_i, or f*_i + g_i where the fluid pass added g
-                                fr[i] = pop_get<S>(fo[i], Dir<i, L>::template w<T>(), rown);
-                                a[i] = T(2) * fr[i] + gp * Dir<i, L>::template w<T>() * pn[i];
-                            }
-                        }
-                    });
+                    }
                 }
-            } else if (rep) {
-                // a solid node of body b1 within r_c of the solid radius of a body b2 > b1 may
-                // have solid nodes of b2 within r_c: both bodies are marked, and the per-body
-                // pass below finds the pairs (a pair-free mark adds zeros)
-                b1 = owner_of(w0);
-                for (int b2 = b1 + 1; b2 < nbod; ++b2) {
-                    const double *BX = bt[wave][b2];
+                const uint64_t bal = __ballot(need);
+                if (need) keep[wave][nkeep + __popcll(bal & ((1ull << lane) - 1ull))] = run + 64 * u + lane;
+                nkeep += __popcll(bal);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int j0 = 0; j0 < nkeep; j0 += 64) {
+            const bool has = j0 + lane < nkeep;
+            const int k = has ? keep[wave][j0 + lane] : 0;
+            uint32_t touched = 0;
+            int x = 0, y = 0, z = 0, idx = 0, b1 = -1;
+            uint32_t nbits = 0;  // solid-neighbour bits of a fluid node
+            bool fluid = false;
+            T rho = T(0), ps0 = T(0), rown = T(0), drho = T(0);
+            // per link i into a solid neighbour: its owner (4-bit fields), the reflected post-collision
+            // population fr_i = f*_i and the body-independent part of the link force, a_i = 2 f*_i +
+            // G psi(x) w_i psi(x + c_i); drho sums the moving-wall terms of the node's links
+            uint32_t own[(L::Q + 7) / 8] = {};
+            T a[L::Q], fr[L::Q];
+            if (has) {
+                int u[3], c[3];
+                it.cell(k, u, c);
+                x = c[0];
+                y = c[1];
+                z = c[2];
+                idx = x + nx * (y + ny * z);
+                const cell_t w0 = mask[idx];
+                if (!(w0 & C_SOLID)) {
+                    fluid = true;
+                    uint32_t mo[L::Q];  // words of the neighbours
+                    const NbrU ne(x, y, z, nx, ny, nz, 1);
+                    if constexpr (L::kBits)
+                        nbits = w0 & C_NBMASK;
+                    else
+                        nbits = nbw[idx];
+                    if (nbits) {
+                        // Every gather of the node is issued in one round and unconditionally (the
+                        // neighbour values are cache-served), so the per-link selects below wait for
+                        // memory once; loads inside the per-link branches were serialised, one
+                        // memory latency per link.
+                        const uint32_t ib = (uint32_t)idx * (uint32_t)sizeof(T);
+                        const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
+                        S fo[L::Q];  // reflected populations f*_i, in slot opp(i), written by the fluid pass
+                        T pn[L::Q];  // neighbour pseudopotentials
+                        sfor<L::Q>([&](auto I) {
+                            constexpr int i = decltype(I)::value;
+                            if constexpr (i > 0) {
+                                const uint32_t n = ne.template at<i>((uint32_t)idx);
+                                mo[i] = ldb(mask, n * 4u);
+                                fo[i] = ldb(fpost + (long long)Dir<i, L>::opp * Np, is);
+                                pn[i] = ldb(psi, n * (uint32_t)sizeof(T));
+                            }
+                        });
+                        rho = sizeof(S) == 2 ? ref_density(psi_prev[idx], p.rho0) : T(0);
+                        sfor<L::Q>([&](auto I) { rho += (T)ldb(fin + (long long)I * Np, is); });
+                        ps0 = ldb(psi, ib);
+                        rown = sizeof(S) == 2 ? ref_density(ps0, p.rho0) : T(0);
+                        const T gp = p.G * ps0;
+                        sfor<L::Q>([&](auto I) {
+                            constexpr int i = decltype(I)::value;
+                            a[i] = T(0);
+                            fr[i] = T(0);
+                            if constexpr (i > 0) {
+                                if (nbits & (1u << i)) {
+                                    const uint32_t o = (uint32_t)owner_of(mo[i]);
+                                    own[i >> 3] |= o << (4 * (i & 7));
+                                    touched |= 1u << o;
+                                    // reflected value: f*_i, or f*_i + g_i where the fluid pass added g
+                                    fr[i] = pop_get<S>(fo[i], Dir<i, L>::template w<T>(), rown);
+                                    a[i] = T(2) * fr[i] + gp * Dir<i, L>::template w<T>() * pn[i];
+                                }
+                            }
+                        });
+                    }
+                } else if (rep) {
+                    // a solid node of body b1 within r_c of the solid radius of a body b2 > b1 may
+                    // have solid nodes of b2 within r_c: both bodies are marked, and the per-body
+                    // pass below finds the pairs (a pair-free mark adds zeros)
+                    b1 = owner_of(w0);
+                    for (int b2 = b1 + 1; b2 < nbod; ++b2) {
+                        const double *BX = bt[wave][b2];
+                        const double rx = mimg_r(x - BX[0], nx, p.inv_n[0]), ry = mimg_r(y - BX[1], ny, p.inv_n[1]),
+                                     rz = mimg_r(z - BX[2], nz, p.inv_n[2]);
+                        if (sqrt(rx * rx + ry * ry + rz * rz) < (double)st->srad[b2] + rc + 1e-3)
+                            touched |= (1u << b1) | (1u << b2);
+                    }
+                }
+            }
+            uint32_t wt = wave_or(touched);
+            while (wt) {
+                const int b = __ffs(wt) - 1;
+                wt &= wt - 1;
+                double v[6] = {0, 0, 0, 0, 0, 0};
+                if ((touched & (1u << b)) && fluid) {
+                    // The link midpoint is x + c_i/2, so with r the node's offset from the centre:
+                    // c_i . u_w(x + c_i/2) = c_i . u_w(x) (the term c_i . (W x c_i)/2 vanishes) and
+                    // (r + c_i/2) x s c_i = r x s c_i.  The wall term needs the node's rigid velocity
+                    // only, and the torque is r x (sum of the link forces).
+                    const double *BX = bt[wave][b], *BV = BX + 3, *BW = BX + 6;
                     const double rx = mimg_r(x - BX[0], nx, p.inv_n[0]), ry = mimg_r(y - BX[1], ny, p.inv_n[1]),
                                  rz = mimg_r(z - BX[2], nz, p.inv_n[2]);
-                    if (sqrt(rx * rx + ry * ry + rz * rz) < (double)st->srad[b2] + rc + 1e-3)
-                        touched |= (1u << b1) | (1u << b2);
-                }
-            }
-        }
-        uint32_t wt = wave_or(touched);
-        while (wt) {
-            const int b = __ffs(wt) - 1;
-            wt &= wt - 1;
-            double v[6] = {0, 0, 0, 0, 0, 0};
-            if ((touched & (1u << b)) && fluid) {
-                // The link midpoint is x + c_i/2, so with r the node's offset from the centre:
-                // c_i . u_w(x + c_i/2) = c_i . u_w(x) (the term c_i . (W x c_i)/2 vanishes) and
-                // (r + c_i/2) x s c_i = r x s c_i.  The wall term needs the node's rigid velocity
-                // only, and the torque is r x (sum of the link forces).
-                const double *BX = bt[wave][b], *BV = BX + 3, *BW = BX + 6;
-                const double rx = mimg_r(x - BX[0], nx, p.inv_n[0]), ry = mimg_r(y - BX[1], ny, p.inv_n[1]),
-                             rz = mimg_r(z - BX[2], nz, p.inv_n[2]);
-                const double u0x = BV[0] + (BW[1] * rz - BW[2] * ry), u0y = BV[1] + (BW[2] * rx - BW[0] * rz),
-                             u0z = BV[2] + (BW[0] * ry - BW[1] * rx);
-                double fx = 0.0, fy = 0.0, fz = 0.0;
-                sfor<L::Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    if constexpr (i > 0) {
-                        if ((nbits & (1u << i)) && ((own[i >> 3] >> (4 * (i & 7))) & 15u) == (uint32_t)b) {
-                            double cuw = 0.0;
-                            if constexpr (Dir<i, L>::x != 0) cuw += Dir<i, L>::x * u0x;
-                            if constexpr (Dir<i, L>::y != 0) cuw += Dir<i, L>::y * u0y;
-                            if constexpr (Dir<i, L>::z != 0) cuw += Dir<i, L>::z * u0z;
-                            // moving-wall term g: the reflected population becomes f*_i + g (Sec.
-                            // 3.2.2); the link carries 2 f*_i + g to the body plus the
-                            // pseudopotential reaction, both along c_i
-                            const T g = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
-                            double s;
-                            if constexpr (!wall_in_fluid_pass<S>()) {
-                                stb(fpost + (long long)Dir<i, L>::opp * Np, (uint32_t)idx * (uint32_t)sizeof(S),
-                                    pop_put<S>(fr[i] + g, Dir<i, L>::template w<T>(), rown));
-                                drho += g;
-                                s = (double)(a[i] + g);
-                            } else {
-                                s = (double)(a[i] - g);  // 2 (f*_i + g) - g
+                    const double u0x = BV[0] + (BW[1] * rz - BW[2] * ry), u0y = BV[1] + (BW[2] * rx - BW[0] * rz),
+                                 u0z = BV[2] + (BW[0] * ry - BW[1] * rx);
+                    double fx = 0.0, fy = 0.0, fz = 0.0;
+                    sfor<L::Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        if constexpr (i > 0) {
+                            if ((nbits & (1u << i)) && ((own[i >> 3] >> (4 * (i & 7))) & 15u) == (uint32_t)b) {
+                                double cuw = 0.0;
+                                if constexpr (Dir<i, L>::x != 0) cuw += Dir<i, L>::x * u0x;
+                                if constexpr (Dir<i, L>::y != 0) cuw += Dir<i, L>::y * u0y;
+                                if constexpr (Dir<i, L>::z != 0) cuw += Dir<i, L>::z * u0z;
+                                // moving-wall term g: the reflected population becomes f*_i + g (Sec.
+                                // 3.2.2); the link carries 2 f*_i + g to the body plus the
+                                // pseudopotential reaction, both along c_i
+                                const T g = T(-6.0 * Dir<i, L>::template w<double>() * cuw) * rho;
+                                double s;
+                                if constexpr (!wall_in_fluid_pass<S>()) {
+                                    stb(fpost + (long long)Dir<i, L>::opp * Np, (uint32_t)idx * (uint32_t)sizeof(S),
+                                        pop_put<S>(fr[i] + g, Dir<i, L>::template w<T>(), rown));
+                                    drho += g;
+                                    s = (double)(a[i] + g);
+                                } else {
+                                    s = (double)(a[i] - g);  // 2 (f*_i + g) - g
+                                }
+                                if constexpr (Dir<i, L>::x == 1) fx += s;
+                                if constexpr (Dir<i, L>::x == -1) fx -= s;
+                                if constexpr (Dir<i, L>::y == 1) fy += s;
+                                if constexpr (Dir<i, L>::y == -1) fy -= s;
+                                if constexpr (Dir<i, L>::z == 1) fz += s;
+                                if constexpr (Dir<i, L>::z == -1) fz -= s;
                             }
-                            if constexpr (Dir<i, L>::x == 1) fx += s;
-                            if constexpr (Dir<i, L>::x == -1) fx -= s;
-                            if constexpr (Dir<i, L>::y == 1) fy += s;
-                            if constexpr (Dir<i, L>::y == -1) fy -= s;
-                            if constexpr (Dir<i, L>::z == 1) fz += s;
-                            if constexpr (Dir<i, L>::z == -1) fz -= s;
+                        }
+                    });
+                    v[0] = fx;
+                    v[1] = fy;
+                    v[2] = fz;
+                    v[3] = ry * fz - rz * fy;
+                    v[4] = rz * fx - rx * fz;
+                    v[5] = rx * fy - ry * fx;
+                } else if (touched & (1u << b)) {
+                    // repulsion between this solid node p of body b1 and the solid nodes q = p + d of
+                    // bodies above b1: on b1 at p (b == b1), or the reaction on b at q (b != b1).  With
+                    // r the offset of p from the centre of b, the torque is r x (sum f) for b1 and
+                    // r x (sum f) + sum d x f for the reaction, so each pair costs a few additions.
+                    const bool react = b != b1;
+                    double sfx = 0.0, sfy = 0.0, sfz = 0.0, tdx = 0.0, tdy = 0.0, tdz = 0.0;
+                    const int nrep = st->n_rep;
+                    for (int j0 = 0; j0 < nrep; j0 += RC) {
+                        cell_t mqs[RC];
+    #pragma unroll
+                        for (int j = 0; j < RC; ++j) {
+                            const int o = st->rep_off[j0 + j < nrep ? j0 + j : j0];
+                            const int dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
+                            mqs[j] = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
+                        }
+    #pragma unroll
+                        for (int j = 0; j < RC; ++j) {
+                            if (j0 + j >= nrep) break;
+                            const cell_t mq = mqs[j];
+                            if (!(mq & C_SOLID)) continue;
+                            const int b2 = owner_of(mq);
+                            if (b2 <= b1 || (react && b != b2)) continue;
+                            // force on b1 at p, directed from q to p; its opposite on b2 at q
+                            const double sg = react ? -1.0 : 1.0;
+                            const double fx = sg * st->rep_f[j0 + j][0], fy = sg * st->rep_f[j0 + j][1],
+                                         fz = sg * st->rep_f[j0 + j][2];
+                            sfx += fx;
+                            sfy += fy;
+                            sfz += fz;
+                            if (react) {
+                                const int o = st->rep_off[j0 + j];
+                                const double dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
+                                tdx += dy * fz - dz * fy;
+                                tdy += dz * fx - dx * fz;
+                                tdz += dx * fy - dy * fx;
+                            }
                         }
                     }
-                });
-                v[0] = fx;
-                v[1] = fy;
-                v[2] = fz;
-                v[3] = ry * fz - rz * fy;
-                v[4] = rz * fx - rx * fz;
-                v[5] = rx * fy - ry * fx;
-            } else if (touched & (1u << b)) {
-                // repulsion between this solid node p of body b1 and the solid nodes q = p + d of
-                // bodies above b1: on b1 at p (b == b1), or the reaction on b at q (b != b1).  With
-                // r the offset of p from the centre of b, the torque is r x (sum f) for b1 and
-                // r x (sum f) + sum d x f for the reaction, so each pair costs a few additions.
-                const bool react = b != b1;
-                double sfx = 0.0, sfy = 0.0, sfz = 0.0, tdx = 0.0, tdy = 0.0, tdz = 0.0;
-                const int nrep = st->n_rep;
-                for (int j0 = 0; j0 < nrep; j0 += RC) {
-                    cell_t mqs[RC];
-#pragma unroll
-                    for (int j = 0; j < RC; ++j) {
-                        const int o = st->rep_off[j0 + j < nrep ? j0 + j : j0];
-                        const int dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
-                        mqs[j] = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
-                    }
-#pragma unroll
-                    for (int j = 0; j < RC; ++j) {
-                        if (j0 + j >= nrep) break;
-                        const cell_t mq = mqs[j];
-                        if (!(mq & C_SOLID)) continue;
-                        const int b2 = owner_of(mq);
-                        if (b2 <= b1 || (react && b != b2)) continue;
-                        // force on b1 at p, directed from q to p; its opposite on b2 at q
-                        const double sg = react ? -1.0 : 1.0;
-                        const double fx = sg * st->rep_f[j0 + j][0], fy = sg * st->rep_f[j0 + j][1],
-                                     fz = sg * st->rep_f[j0 + j][2];
-                        sfx += fx;
-                        sfy += fy;
-                        sfz += fz;
-                        if (react) {
-                            const int o = st->rep_off[j0 + j];
-                            const double dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
-                            tdx += dy * fz - dz * fy;
-                            tdy += dz * fx - dx * fz;
-                            tdz += dx * fy - dy * fx;
-                        }
-                    }
+                    const double *BX = bt[wave][b];
+                    const double rx = mimg(x - BX[0], nx), ry = mimg(y - BX[1], ny), rz = mimg(z - BX[2], nz);
+                    v[0] = sfx;
+                    v[1] = sfy;
+                    v[2] = sfz;
+                    v[3] = ry * sfz - rz * sfy + tdx;
+                    v[4] = rz * sfx - rx * sfz + tdy;
+                    v[5] = rx * sfy - ry * sfx + tdz;
                 }
-                const double *BX = bt[wave][b];
-                const double rx = mimg(x - BX[0], nx), ry = mimg(y - BX[1], ny), rz = mimg(z - BX[2], nz);
-                v[0] = sfx;
-                v[1] = sfy;
-                v[2] = sfz;
-                v[3] = ry * sfz - rz * sfy + tdx;
-                v[4] = rz * sfx - rx * sfz + tdy;
-                v[5] = rx * sfy - ry * sfx + tdz;
+    #pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double s = wave_sum(v[c]);
+                    if (lane == 0) acc[wave][b][c] += s;
+                }
             }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const double s = wave_sum(v[c]);
-                if (lane == 0) acc[wave][b][c] += s;
+            if (!wall_in_fluid_pass<S>() && fluid && nbits) {
+                // the rest population gives back the moving-wall terms (mass correction, Sec. 3.2.2)
+                const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
+                const T f0 = pop_get<S>(ldb(fpost, is), Dir<0, L>::template w<T>(), rown);
+                stb(fpost, is, pop_put<S>(f0 - drho, Dir<0, L>::template w<T>(), rown));
             }
         }
-        if (!wall_in_fluid_pass<S>() && fluid && nbits) {
-            // the rest population gives back the moving-wall terms (mass correction, Sec. 3.2.2)
-            const uint32_t is = (uint32_t)idx * (uint32_t)sizeof(S);
-            const T f0 = pop_get<S>(ldb(fpost, is), Dir<0, L>::template w<T>(), rown);
-            stb(fpost, is, pop_put<S>(f0 - drho, Dir<0, L>::template w<T>(), rown));
-        }
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     for (int k = tid; k < nbod * 6; k += NT) {
