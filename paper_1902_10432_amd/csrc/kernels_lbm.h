@@ -637,16 +637,18 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
     const long long Np = p.Np;
     const bool rep = nbod > 1 && (p.flags & PF_LBM_REPULSION);
     const double rc = p.r_c;
-    constexpr int RC = 16;  // repulsion offsets per round of loads
-    // Each wave takes runs of 64 U consecutive box cells.  A first pass loads their cell words in
-    // one round and keeps the cells that need the per-link (or repulsion) work: fluid cells with a
-    // solid neighbour, and solid cells within r_c of the solid radius of a higher-index body.  The
-    // second pass runs that work on the kept cells only, 64 per round, so the cells without a link
-    // cost one load in a wide round instead of a pass of the scan each.
+    constexpr int RC = 32;  // repulsion offsets per round of loads
+    // Each wave takes U rows of 64 consecutive box cells, the rows nw * 64 cells apart (nw waves in
+    // the grid), so that the cells with work -- clustered on the bodies' surfaces and, for the
+    // repulsion, in the small caps where two bodies nearly touch -- spread over all waves.  A first
+    // pass loads the U cell words of each lane in one round and keeps the cells that need the
+    // per-link (or repulsion) work: fluid cells with a solid neighbour, and solid cells within r_c of
+    // the solid radius of a higher-index body.  The second pass runs that work on the kept cells
+    // only, 64 per round, so the cells without a link cost one load in a wide round each.
     constexpr int U = 8;
     __shared__ int keep[W][64 * U];
     const int gw = (int)blockIdx.x * W + wave, nw = (int)gridDim.x * W;
-    for (int run = gw * 64 * U; run < it.vol; run += nw * 64 * U) {
+    for (int run = gw * 64; run < it.vol; run += nw * 64 * U) {
         int nkeep = 0;
         {
             cell_t wk[U];
@@ -654,7 +656,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
             bool in[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int k = run + 64 * u + lane;
+                const int k = run + nw * 64 * u + lane;
                 in[u] = k < it.vol;
                 int uu[3];
                 it.cell(in[u] ? k : 0, uu, ck[u]);
@@ -686,7 +688,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                     }
                 }
                 const uint64_t bal = __ballot(need);
-                if (need) keep[wave][nkeep + __popcll(bal & ((1ull << lane) - 1ull))] = run + 64 * u + lane;
+                if (need) keep[wave][nkeep + __popcll(bal & ((1ull << lane) - 1ull))] = run + nw * 64 * u + lane;
                 nkeep += __popcll(bal);
             }
         }
