@@ -647,6 +647,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
     // only, 64 per round, so the cells without a link cost one load in a wide round each.
     constexpr int U = 8;
     __shared__ int keep[W][64 * U];
+    __shared__ double rsum[W][9][64];  // per-lane repulsion sums of the current round
     const int gw = (int)blockIdx.x * W + wave, nw = (int)gridDim.x * W;
     for (int run = gw * 64; run < it.vol; run += nw * 64 * U) {
         int nkeep = 0;
@@ -698,6 +699,9 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
             const int k = has ? keep[wave][j0 + lane] : 0;
             uint32_t touched = 0;
             int x = 0, y = 0, z = 0, idx = 0, b1 = -1;
+            // repulsion of a solid node p of body b1: the first body rb2 > b1 met in the search
+            int rb2 = -1;
+            bool rmulti = false;
             uint32_t nbits = 0;  // solid-neighbour bits of a fluid node
             bool fluid = false;
             T rho = T(0), ps0 = T(0), rown = T(0), drho = T(0);
@@ -773,6 +777,54 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                         if (sqrt(rx * rx + ry * ry + rz * rz) < (double)st->srad[b2] + rc + 1e-3)
                             touched |= (1u << b1) | (1u << b2);
                     }
+                    if (touched) {
+                        // one pass over the offsets within r_c: the force on b1 from every body
+                        // above it (rs1), and the reaction on the first such body met with its
+                        // lever-arm part sum d x f (rs2, rt2), kept in the lane's LDS slots for the
+                        // per-body loop; a second body met gets its reaction from a pass of its own
+                        double rs1[3] = {0.0, 0.0, 0.0}, rs2[3] = {0.0, 0.0, 0.0}, rt2[3] = {0.0, 0.0, 0.0};
+                        const int nrep = st->n_rep;
+                        for (int j0 = 0; j0 < nrep; j0 += RC) {
+                            cell_t mqs[RC];
+#pragma unroll
+                            for (int j = 0; j < RC; ++j) {
+                                const int o = st->rep_off[j0 + j < nrep ? j0 + j : j0];
+                                const int dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
+                                mqs[j] = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
+                            }
+#pragma unroll
+                            for (int j = 0; j < RC; ++j) {
+                                if (j0 + j >= nrep) break;
+                                const cell_t mq = mqs[j];
+                                if (!(mq & C_SOLID)) continue;
+                                const int b2 = owner_of(mq);
+                                if (b2 <= b1) continue;
+                                rs1[0] += st->rep_f[j0 + j][0];
+                                rs1[1] += st->rep_f[j0 + j][1];
+                                rs1[2] += st->rep_f[j0 + j][2];
+                                if (rb2 < 0) rb2 = b2;
+                                if (b2 != rb2) {
+                                    rmulti = true;
+                                    continue;
+                                }
+                                const double fx = -1.0 * st->rep_f[j0 + j][0], fy = -1.0 * st->rep_f[j0 + j][1],
+                                             fz = -1.0 * st->rep_f[j0 + j][2];
+                                rs2[0] += fx;
+                                rs2[1] += fy;
+                                rs2[2] += fz;
+                                const int o = st->rep_off[j0 + j];
+                                const double dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
+                                rt2[0] += dy * fz - dz * fy;
+                                rt2[1] += dz * fx - dx * fz;
+                                rt2[2] += dx * fy - dy * fx;
+                            }
+                        }
+                        for (int c = 0; c < 3; ++c) {
+                            rsum[wave][c][lane] = rs1[c];
+                            rsum[wave][3 + c][lane] = rs2[c];
+                            rsum[wave][6 + c][lane] = rt2[c];
+                        }
+                    }
                 }
             }
             uint32_t wt = wave_or(touched);
@@ -834,16 +886,29 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                     // r x (sum f) + sum d x f for the reaction, so each pair costs a few additions.
                     const bool react = b != b1;
                     double sfx = 0.0, sfy = 0.0, sfz = 0.0, tdx = 0.0, tdy = 0.0, tdz = 0.0;
-                    const int nrep = st->n_rep;
+                    if (b == b1) {
+                        sfx = rsum[wave][0][lane];
+                        sfy = rsum[wave][1][lane];
+                        sfz = rsum[wave][2][lane];
+                    } else if (b == rb2) {
+                        sfx = rsum[wave][3][lane];
+                        sfy = rsum[wave][4][lane];
+                        sfz = rsum[wave][5][lane];
+                        tdx = rsum[wave][6][lane];
+                        tdy = rsum[wave][7][lane];
+                        tdz = rsum[wave][8][lane];
+                    }
+                    // the reaction on a further body (rare): a pass of its own
+                    const int nrep = react && b != rb2 && rmulti ? st->n_rep : 0;
                     for (int j0 = 0; j0 < nrep; j0 += RC) {
                         cell_t mqs[RC];
-    #pragma unroll
+#pragma unroll
                         for (int j = 0; j < RC; ++j) {
                             const int o = st->rep_off[j0 + j < nrep ? j0 + j : j0];
                             const int dx = (o & 255) - 8, dy = ((o >> 8) & 255) - 8, dz = (o >> 16) - 8;
                             mqs[j] = mask[wrapi(x + dx, nx) + nx * (wrapi(y + dy, ny) + ny * wrapi(z + dz, nz))];
                         }
-    #pragma unroll
+#pragma unroll
                         for (int j = 0; j < RC; ++j) {
                             if (j0 + j >= nrep) break;
                             const cell_t mq = mqs[j];
@@ -875,7 +940,7 @@ __global__ __launch_bounds__((64 * force_waves<ArT<S>, L>())) void k_body_forces
                     v[4] = rz * sfx - rx * sfz + tdy;
                     v[5] = rx * sfy - ry * sfx + tdz;
                 }
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     const double s = wave_sum(v[c]);
                     if (lane == 0) acc[wave][b][c] += s;
