@@ -584,10 +584,13 @@ int pf_lbm_init(const pf_lbm_config *cfg, int32_t n_bodies, const pf_lbm_body *b
     const int box_blocks = (int)std::max(1LL, std::min(4096LL, (3 * vol0 / 2 + 255) / 256));
     const int box_grid = box_blocks;
     const int force_grid = std::min((box_blocks + 3) / 4, FORCE_GRID_MAX);
-    // phase update (and the classification partials it leaves): grid-stride over the tiles with
-    // two blocks per CU, four for boxes above 2^20 cells; more blocks were measured slower (each
-    // block's partials are summed at the start of the next step)
-    const int cgrid = std::min(box_blocks, vol0 > (1LL << 20) ? 1024 : 512);
+    // phase update (and the classification partials it leaves): grid-stride over the tiles.  With
+    // up to 4 bodies and a box above 2^19 cells, three 4-wave blocks per CU, as many as a CU holds
+    // at that variant's registers, in one round (four per CU ran a second round and were no
+    // faster); otherwise two blocks per CU, four for boxes above 2^20 cells.  Each block's partials
+    // are summed at the start of the next step, so more blocks cost there.
+    const int cgrid = std::min(box_blocks, (n_bodies <= 4 && vol0 > (1LL << 19)) ? 768
+                                           : (vol0 > (1LL << 20) ? 1024 : 512));
     const long long ntiles = (long long)((cfg->nx + TLX - 1) / TLX) * ((cfg->ny + TLY - 1) / TLY) * ((cfg->nz + TLZ - 1) / TLZ);
     const Layout L = make_layout(Np, n_bodies, cfg->precision, cfg->lattice, std::max(cgrid, box_grid), force_grid,
                                  ntiles);
